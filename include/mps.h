@@ -1,0 +1,195 @@
+/* mps.h -- C ABI of the MI355X candidate-move evaluation engine.
+ *
+ * Problem statement (paper Sec. 5, Eq. 14-16):
+ *   N = nx*ny*nz blocks, block index b = x + nx*(y + ny*z), z = 0 the top bench;
+ *   a schedule p[b] in {0..T-1} is the period in which block b is mined, and
+ *   p[b] = T means "never mined";
+ *   precedence (Eq. 15) under the 1-5 slope stencil: the predecessors of b are
+ *   the block right above it and the four blocks sharing a face with that
+ *   block (bench z-1, clipped at the grid edges); p[a] <= p[b] for each of them;
+ *   S geological scenarios give block values v[s][b] ($) and ore indicators
+ *   ore[s][b] (block processed in scenario s); ton[b] is the block tonnage.
+ *
+ * Objective of a schedule (the expectation of Eq. 14, risk-adjusted, with the
+ * capacity constraints of Eq. 16 and of the processing plant as penalties):
+ *   d(t) = (1+rate)^-t for t < T, d(T) = 0       (Alg. 5 discounts by 1.08^-t)
+ *   N_s  = sum_b v[s][b] d(p_b),  mu = mean_s N_s,  sigma = population std
+ *   O[s][t] = sum_{b: p_b=t} ton_b ore[s][b],  M[t] = sum_{b: p_b=t} ton_b
+ *   J = mu - lambda*sigma - pen_proc/S * sum_{s,t<T} max(0, O[s][t] - proc_cap)
+ *                         - pen_mine   * sum_{t<T}   max(0, M[t]    - mine_cap)
+ *
+ * A move (b, t') sets p[b] = t'.  Its score is J(p') - J(p); its flags are
+ *   MPS_PREC_OK  every predecessor a has p[a] <= t', every successor c has t' <= p[c]
+ *   MPS_MINE_OK  t' == T or t' == p[b] or M[t'] + ton_b <= mine_cap
+ *   MPS_PROC_OK  t' == T or t' == p[b] or, for every s with ore[s][b],
+ *                O[s][t'] + ton_b <= proc_cap
+ *   MPS_NOOP     t' == p[b]               (score exactly 0)
+ *   MPS_BAD      b outside [0,N) or t' outside [0,T] (score = -FLT_MAX)
+ * This is the per-candidate precedence / capacity / value evaluation of the
+ * paper's Alg. 5, made exact and extended to every destination period.
+ *
+ * Conventions.  Every call returns an mps_status; nothing throws across the
+ * ABI.  On a non-OK status mps_last_error() returns a thread-local message.
+ * Array arguments are DEVICE pointers owned by the caller unless stated
+ * otherwise; scalars and structs are host memory.  Calls taking a `stream`
+ * (a hipStream_t; NULL = the default stream) enqueue asynchronously and
+ * neither allocate nor synchronise, unless their comment says otherwise.
+ * Host-detectable argument errors return MPS_E_INVALID_ARG before any work
+ * is enqueued.  Data errors found on the device never abort: they are
+ * reported in outputs (BAD flags, violation counts). */
+#ifndef MPS_H
+#define MPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPS_OK = 0,
+    MPS_E_INVALID_ARG = 1,
+    MPS_E_OUT_OF_MEMORY = 2,
+    MPS_E_DEVICE = 3,
+    MPS_E_INFEASIBLE = 4,
+    MPS_E_NOT_CAPTURABLE = 5,
+    MPS_E_INTERNAL = 6
+} mps_status;
+
+enum {
+    MPS_PREC_OK = 1,
+    MPS_MINE_OK = 2,
+    MPS_PROC_OK = 4,
+    MPS_NOOP = 8,
+    MPS_BAD = 16
+};
+
+/* Limits enforced by the host checks. */
+#define MPS_MAX_PERIODS 126          /* T; periods are int8 with T = never */
+#define MPS_MAX_SCENARIOS 4096       /* S */
+#define MPS_MAX_TOPK 8192            /* k of mps_topk / mps_rank_moves */
+
+typedef struct mps_model mps_model;
+
+typedef struct {
+    int32_t nx, ny, nz;      /* grid; N = nx*ny*nz >= 1 */
+    int32_t n_scen;          /* S, 1..MPS_MAX_SCENARIOS */
+    int32_t n_periods;       /* T, 1..MPS_MAX_PERIODS; destination T = never */
+    int32_t reserved;        /* must be 0 */
+    double discount_rate;    /* per period, > -1 (0.08 in the paper) */
+    double lambda;           /* weight of the std, finite */
+    double pen_proc;         /* $ per tonne of processing excess, >= 0 */
+    double pen_mine;         /* $ per tonne of mining excess, >= 0 */
+    double proc_cap;         /* tonnes per period */
+    double mine_cap;         /* tonnes per period */
+} mps_params;
+
+typedef struct {
+    double mu, sigma, R, Pp, Pm, J;  /* R = mu - lambda*sigma, J = R - Pp - Pm */
+    int64_t n_prec_viol;             /* predecessor pairs with p[a] > p[b] */
+} mps_objective;
+
+/* A set of moves.  exhaustive != 0: move i is (i / D, i % D) for
+ * i in [0, N*D), D = T+1 if include_never else T (block, period ignored).
+ * Otherwise the n moves (block[i], period[i]) given as device arrays. */
+typedef struct {
+    int32_t exhaustive;
+    int32_t include_never;
+    int64_t n;
+    const int32_t *block;
+    const int8_t *period;
+} mps_moves;
+
+/* Penalty weights of the relaxed objective (see mps_relaxed_fwd). */
+typedef struct {
+    double mu_proc, mu_mine, mu_prec;
+} mps_relax_params;
+
+/* Thread-local text of the last error ("" if none). */
+const char *mps_last_error(void);
+
+/* ABI version (major*100 + minor). */
+int32_t mps_version(void);
+
+/* Number of visible GPUs; MPS_E_DEVICE (and *n = 0) when there is none. */
+mps_status mps_device_count(int32_t *n);
+
+/* Build a model from device arrays on the current device (Sec. 5 parameters):
+ *   v        float [S][N]     block values, scenario-major;
+ *   ore_bits uint32 [ceil(S/32)][N]; scenario s is bit s%32 of word s/32;
+ *   ton      double [N]       tonnages, > 0.
+ * The model copies what it keeps (the caller may free its arrays afterwards),
+ * derives per-block statistics, allocates every buffer later calls need, and
+ * starts with the schedule "everything in period 0".  Synchronises `stream`.
+ * Not capturable. */
+mps_status mps_build_model(const mps_params *prm, const float *v,
+                           const uint32_t *ore_bits, const double *ton,
+                           void *stream, mps_model **out);
+
+/* Free a model and its device memory (synchronises the device). */
+mps_status mps_destroy_model(mps_model *m);
+
+/* Problem size of a model. */
+mps_status mps_model_dims(const mps_model *m, int64_t *N, int32_t *S, int32_t *T);
+
+/* Load schedule p (device int8 [N], values 0..T) and derive the state
+ * (per-scenario NPV, period tonnages, penalty tables).  Values outside
+ * 0..T are clamped to T and counted as violations in mps_get_objective. */
+mps_status mps_set_schedule(mps_model *m, const int8_t *p, void *stream);
+
+/* Copy the model's current schedule into p (device int8 [N]). */
+mps_status mps_get_schedule(mps_model *m, int8_t *p, void *stream);
+
+/* Objective of the current schedule into a HOST struct (synchronises). */
+mps_status mps_get_objective(mps_model *m, mps_objective *out, void *stream);
+
+/* Objective terms of the current schedule into DEVICE memory
+ * (double[7]: mu, sigma, R, Pp, Pm, J, n_prec_viol); capturable. */
+mps_status mps_objective_async(mps_model *m, double *out, void *stream);
+
+/* Evaluate moves against the current schedule (Alg. 5, every destination):
+ *   score  float [n_moves]  J(p') - J(p), FP32 arithmetic on FP64 state;
+ *   flags  uint8 [n_moves]  MPS_* bits;
+ *   d_risk, d_pen_proc, d_pen_mine  float [n_moves] or NULL: the change of
+ *          mu - lambda*sigma and of the two penalty terms (score =
+ *          d_risk - d_pen_proc - d_pen_mine).
+ * n_moves = N*D (exhaustive) or moves->n.  Output index = move index. */
+mps_status mps_eval_moves(mps_model *m, const mps_moves *moves, float *score,
+                          uint8_t *flags, float *d_risk, float *d_pen_proc,
+                          float *d_pen_mine, void *stream);
+
+/* Workspace bytes mps_topk needs for n items and k selected. */
+size_t mps_topk_ws_bytes(int64_t n, int32_t k);
+
+/* Top-k selection (the argmax reduction of Alg. 5 generalised to k):
+ * keep items i with (flags[i] & require) == require and (flags[i] & forbid)
+ * == 0 (NaN scores never qualify); order by score descending, then index
+ * ascending; write the first min(k, #kept) to idx (int64 [k]) and top_score
+ * (float [k], may be NULL), and that count to *count (device int32).
+ * Entries past the count are set to -1 / -inf.  1 <= k <= MPS_MAX_TOPK,
+ * 0 <= n < 2^31.  ws: device workspace of mps_topk_ws_bytes(n, k) bytes. */
+mps_status mps_topk(const float *score, const uint8_t *flags, int64_t n,
+                    int32_t k, uint8_t require, uint8_t forbid, int64_t *idx,
+                    float *top_score, int32_t *count, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* Greedy repair (Alg. 4 amortised over an ordered candidate list): walk the
+ * candidates idx[0 .. *count) (device int32 count, at most max_cand) that
+ * index into `moves`, in order; skip a block already moved in this call;
+ * re-check precedence and re-score the move exactly (FP64) against the
+ * current schedule and state; apply it iff PREC_OK (and MINE_OK and PROC_OK
+ * when hard_capacity != 0) and its score is > 0, updating the schedule and
+ * state in place.  *applied (device int32, may be NULL) receives the number
+ * of applied moves.  The state is held on chip during the walk: the call
+ * returns MPS_E_INVALID_ARG when 8*S*(T+1) bytes plus a hash map of
+ * 5*2*max_cand bytes exceed one workgroup's LDS; max_cand <= MPS_MAX_TOPK. */
+mps_status mps_repair(mps_model *m, const mps_moves *moves,
+                      const int64_t *idx, const int32_t *count,
+                      int32_t max_cand, int32_t hard_capacity,
+                      int32_t *applied, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPS_H */

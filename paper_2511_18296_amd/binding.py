@@ -1,0 +1,275 @@
+"""ctypes binding of libmps (include/mps.h): argument marshalling only.
+
+Every computation runs in the HIP library; torch supplies device memory and
+the current stream.  Importing this module loads libmps.so and raises if it
+is missing, so a missing build can never fall back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmps.so")
+
+PREC_OK, MINE_OK, PROC_OK, NOOP, BAD = 1, 2, 4, 8, 16
+MAX_PERIODS, MAX_SCENARIOS, MAX_TOPK = 126, 4096, 8192
+
+STATUS = {0: "MPS_OK", 1: "MPS_E_INVALID_ARG", 2: "MPS_E_OUT_OF_MEMORY",
+          3: "MPS_E_DEVICE", 4: "MPS_E_INFEASIBLE", 5: "MPS_E_NOT_CAPTURABLE",
+          6: "MPS_E_INTERNAL"}
+
+
+class MpsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("n_scen", C.c_int32), ("n_periods", C.c_int32),
+                ("reserved", C.c_int32), ("discount_rate", C.c_double),
+                ("lam", C.c_double), ("pen_proc", C.c_double),
+                ("pen_mine", C.c_double), ("proc_cap", C.c_double),
+                ("mine_cap", C.c_double)]
+
+
+class Objective(C.Structure):
+    _fields_ = [("mu", C.c_double), ("sigma", C.c_double), ("R", C.c_double),
+                ("Pp", C.c_double), ("Pm", C.c_double), ("J", C.c_double),
+                ("n_prec_viol", C.c_int64)]
+
+
+class Moves(C.Structure):
+    _fields_ = [("exhaustive", C.c_int32), ("include_never", C.c_int32),
+                ("n", C.c_int64), ("block", C.c_void_p), ("period", C.c_void_p)]
+
+
+class RelaxParams(C.Structure):
+    _fields_ = [("mu_proc", C.c_double), ("mu_mine", C.c_double),
+                ("mu_prec", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "or python paper_2511_18296_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, st = C.c_void_p, C.c_int32, C.c_int64, C.c_int
+    sigs = {
+        "mps_last_error": ([], C.c_char_p),
+        "mps_version": ([], i32),
+        "mps_device_count": ([vp], st),
+        "mps_build_model": ([vp, vp, vp, vp, vp, vp], st),
+        "mps_destroy_model": ([vp], st),
+        "mps_model_dims": ([vp, vp, vp, vp], st),
+        "mps_set_schedule": ([vp, vp, vp], st),
+        "mps_get_schedule": ([vp, vp, vp], st),
+        "mps_get_objective": ([vp, vp, vp], st),
+        "mps_objective_async": ([vp, vp, vp], st),
+        "mps_eval_moves": ([vp, vp, vp, vp, vp, vp, vp, vp], st),
+        "mps_topk_ws_bytes": ([i64, i32], C.c_size_t),
+        "mps_topk": ([vp, vp, i64, i32, C.c_uint8, C.c_uint8, vp, vp, vp, vp,
+                      C.c_size_t, vp], st),
+        "mps_repair": ([vp, vp, vp, vp, i32, i32, vp, vp], st),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+lib = _load()
+
+# every symbol include/mps.h declares (checked by the CPU tests)
+EXPORTS = ("mps_last_error", "mps_version", "mps_device_count", "mps_build_model",
+           "mps_destroy_model", "mps_model_dims", "mps_set_schedule",
+           "mps_get_schedule", "mps_get_objective", "mps_objective_async",
+           "mps_eval_moves", "mps_topk_ws_bytes", "mps_topk", "mps_repair")
+
+
+def check(status: int):
+    if status != 0:
+        raise MpsError(status, lib.mps_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, shape=None, name="array"):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def device_count() -> int:
+    n = C.c_int32(0)
+    lib.mps_device_count(C.byref(n))
+    return n.value
+
+
+@dataclass
+class MoveSet:
+    """Exhaustive (all b*D + t') or an explicit list of (block, period)."""
+    exhaustive: bool = True
+    include_never: bool = True
+    block: torch.Tensor | None = None
+    period: torch.Tensor | None = None
+
+    def c(self) -> Moves:
+        if self.exhaustive:
+            return Moves(1, int(self.include_never), 0, None, None)
+        n = int(self.block.shape[0])
+        return Moves(0, int(self.include_never), n, self.block.data_ptr() if n else None,
+                     self.period.data_ptr() if n else None)
+
+
+class Model:
+    """A block model on the GPU (mps_build_model) with its current schedule."""
+
+    def __init__(self, nx, ny, nz, S, T, v, ore_words, ton, *, rate=0.08, lam=0.5,
+                 pen_proc=100.0, pen_mine=100.0, proc_cap, mine_cap, stream=None):
+        N = nx * ny * nz
+        W = (S + 31) // 32
+        _dev(v, torch.float32, (S, N), "v")
+        _dev(ore_words, torch.int32, (W, N), "ore_words")
+        _dev(ton, torch.float64, (N,), "ton")
+        self.prm = Params(nx, ny, nz, S, T, 0, rate, lam, pen_proc, pen_mine,
+                          proc_cap, mine_cap)
+        self.N, self.S, self.T, self.W = N, S, T, W
+        self.device = v.device
+        h = C.c_void_p()
+        check(lib.mps_build_model(C.byref(self.prm), _ptr(v), _ptr(ore_words),
+                                  _ptr(ton), _stream(stream), C.byref(h)))
+        self.h = h
+        self._objbuf = torch.empty(8, dtype=torch.float64, device=self.device)
+
+    @classmethod
+    def from_instance(cls, inst, device="cuda", stream=None):
+        """Build from a generated instance (numpy arrays copied to the GPU)."""
+        import numpy as np
+        import mpsgen
+        v = torch.from_numpy(np.ascontiguousarray(inst.v)).to(device)
+        words = mpsgen.ore_pack(inst.ore).view(np.int32)
+        ore = torch.from_numpy(np.ascontiguousarray(words)).to(device)
+        ton = torch.from_numpy(np.ascontiguousarray(inst.ton, dtype=np.float64)).to(device)
+        m = cls(inst.nx, inst.ny, inst.nz, inst.S, inst.T, v, ore, ton, rate=inst.rate,
+                lam=inst.lam, pen_proc=inst.pen_proc, pen_mine=inst.pen_mine,
+                proc_cap=inst.pcap, mine_cap=inst.mcap, stream=stream)
+        p = torch.from_numpy(np.ascontiguousarray(inst.p0, dtype=np.int8)).to(device)
+        m.set_schedule(p, stream)
+        return m
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(lib.mps_destroy_model(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def n_moves(self, moves: MoveSet) -> int:
+        if moves.exhaustive:
+            return self.N * (self.T + 1 if moves.include_never else self.T)
+        return int(moves.block.shape[0])
+
+    def set_schedule(self, p, stream=None):
+        _dev(p, torch.int8, (self.N,), "p")
+        check(lib.mps_set_schedule(self.h, _ptr(p), _stream(stream)))
+
+    def get_schedule(self, out=None, stream=None):
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.int8, device=self.device)
+        check(lib.mps_get_schedule(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def objective(self, stream=None) -> dict:
+        o = Objective()
+        check(lib.mps_get_objective(self.h, C.byref(o), _stream(stream)))
+        return dict(mu=o.mu, sigma=o.sigma, R=o.R, Pp=o.Pp, Pm=o.Pm, J=o.J,
+                    n_prec_viol=int(o.n_prec_viol))
+
+    def objective_async(self, out=None, stream=None):
+        out = self._objbuf if out is None else out
+        check(lib.mps_objective_async(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def eval_moves(self, moves: MoveSet | None = None, *, components=False, out=None,
+                   stream=None):
+        moves = moves or MoveSet()
+        if not moves.exhaustive:
+            _dev(moves.block, torch.int32, None, "block")
+            _dev(moves.period, torch.int8, moves.block.shape, "period")
+        n = self.n_moves(moves)
+        if out is None:
+            out = [torch.empty(n, dtype=torch.float32, device=self.device),
+                   torch.empty(n, dtype=torch.uint8, device=self.device)]
+            if components:
+                out += [torch.empty(n, dtype=torch.float32, device=self.device)
+                        for _ in range(3)]
+        comp = out[2:5] if components else [None, None, None]
+        mv = moves.c()
+        check(lib.mps_eval_moves(self.h, C.byref(mv), _ptr(out[0]), _ptr(out[1]),
+                                 *[_ptr(t) for t in comp], _stream(stream)))
+        return tuple(out)
+
+    def repair(self, moves: MoveSet, idx, count, max_cand=None, hard=False, applied=None,
+               stream=None):
+        max_cand = int(idx.shape[0]) if max_cand is None else max_cand
+        if applied is None:
+            applied = torch.zeros(1, dtype=torch.int32, device=self.device)
+        mv = moves.c()
+        check(lib.mps_repair(self.h, C.byref(mv), _ptr(idx), _ptr(count), int(max_cand),
+                             int(bool(hard)), _ptr(applied), _stream(stream)))
+        return applied
+
+
+class TopK:
+    """Reusable top-k buffers (workspace, indices, scores, count)."""
+
+    def __init__(self, n, k, device="cuda"):
+        self.n, self.k = int(n), int(k)
+        self.ws_bytes = int(lib.mps_topk_ws_bytes(self.n, self.k))
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.idx = torch.empty(self.k, dtype=torch.int64, device=device)
+        self.score = torch.empty(self.k, dtype=torch.float32, device=device)
+        self.count = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def __call__(self, score, flags, require=PREC_OK, forbid=NOOP | BAD, stream=None):
+        n = int(score.shape[0])
+        if n > self.n:
+            raise ValueError(f"{n} items exceed the {self.n} this TopK was sized for")
+        _dev(score, torch.float32, None, "score")
+        _dev(flags, torch.uint8, score.shape, "flags")
+        check(lib.mps_topk(_ptr(score), _ptr(flags), n, self.k, require, forbid,
+                           _ptr(self.idx), _ptr(self.score), _ptr(self.count),
+                           _ptr(self.ws), self.ws_bytes, _stream(stream)))
+        return self.idx, self.score, self.count
+
+
+def topk(score, flags, k, require=PREC_OK, forbid=NOOP | BAD, stream=None):
+    t = TopK(score.shape[0], k, score.device)
+    idx, sc, cnt = t(score, flags, require, forbid, stream)
+    c = int(cnt.item())
+    return idx[:c].clone(), sc[:c].clone()

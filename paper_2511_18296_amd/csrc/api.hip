@@ -1,0 +1,456 @@
+// api.hip -- the extern "C" entry points declared in include/mps.h: argument
+// checks, model ownership, workspaces and kernel launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace mps;
+
+namespace {
+
+thread_local std::string g_err;
+
+mps_status fail(mps_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+mps_status dev_fail(hipError_t e, const char *what) {
+    return fail(MPS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Switch to a device for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+    return cs != hipStreamCaptureStatusNone;
+}
+
+bool is_device_ptr(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+struct mps_model {
+    int device = 0;
+    mps_params prm{};
+    DevModel d{};
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    size_t limit = 0;      // test-only allocation cap (0 = none)
+    double *partial = nullptr;
+    int chunks = 8;
+    double *obj_dev = nullptr;   // double[7]
+    int max_lds = 65536;
+
+    template <class T>
+    mps_status alloc(T *&ptr, size_t count) {
+        size_t nbytes = sizeof(T) * (count > 0 ? count : 1);
+        if (limit && bytes + nbytes > limit)
+            return fail(MPS_E_OUT_OF_MEMORY, "allocation of %zu bytes exceeds the test limit",
+                        nbytes);
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, nbytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MPS_E_OUT_OF_MEMORY, "hipMalloc(%zu): %s", nbytes, hipGetErrorString(e));
+        }
+        allocs.push_back(p);
+        bytes += nbytes;
+        ptr = (T *)p;
+        return MPS_OK;
+    }
+    void release() {
+        for (void *p : allocs) hipFree(p);
+        allocs.clear();
+    }
+};
+
+extern "C" {
+
+const char *mps_last_error(void) { return g_err.c_str(); }
+
+int32_t mps_version(void) { return 100; }
+
+mps_status mps_device_count(int32_t *n) {
+    if (!n) return fail(MPS_E_INVALID_ARG, "n is NULL");
+    int c = 0;
+    hipError_t e = hipGetDeviceCount(&c);
+    if (e != hipSuccess || c <= 0) {
+        (void)hipGetLastError();
+        *n = 0;
+        return fail(MPS_E_DEVICE, "no GPU visible (%s)",
+                    e != hipSuccess ? hipGetErrorString(e) : "0 devices");
+    }
+    *n = c;
+    return MPS_OK;
+}
+
+static mps_status check_params(const mps_params *p) {
+    if (!p) return fail(MPS_E_INVALID_ARG, "params is NULL");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+        return fail(MPS_E_INVALID_ARG, "grid dimensions must be >= 1 (got %d x %d x %d)", p->nx,
+                    p->ny, p->nz);
+    int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    if (N > (int64_t)INT32_MAX / 128)
+        return fail(MPS_E_INVALID_ARG, "too many blocks (%lld)", (long long)N);
+    if (p->n_scen < 1 || p->n_scen > MPS_MAX_SCENARIOS)
+        return fail(MPS_E_INVALID_ARG, "n_scen must be in 1..%d (got %d)", MPS_MAX_SCENARIOS,
+                    p->n_scen);
+    if (p->n_periods < 1 || p->n_periods > MPS_MAX_PERIODS)
+        return fail(MPS_E_INVALID_ARG, "n_periods must be in 1..%d (got %d)", MPS_MAX_PERIODS,
+                    p->n_periods);
+    if (p->reserved != 0) return fail(MPS_E_INVALID_ARG, "reserved must be 0");
+    if (!isfinite(p->discount_rate) || p->discount_rate <= -1.0)
+        return fail(MPS_E_INVALID_ARG, "discount_rate must be finite and > -1");
+    if (!isfinite(p->lambda)) return fail(MPS_E_INVALID_ARG, "lambda must be finite");
+    if (!isfinite(p->pen_proc) || p->pen_proc < 0 || !isfinite(p->pen_mine) || p->pen_mine < 0)
+        return fail(MPS_E_INVALID_ARG, "penalties must be finite and >= 0");
+    if (!isfinite(p->proc_cap) || !isfinite(p->mine_cap))
+        return fail(MPS_E_INVALID_ARG, "capacities must be finite");
+    return MPS_OK;
+}
+
+mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t *ore_bits,
+                           const double *ton, void *stream, mps_model **out) {
+    if (!out) return fail(MPS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    mps_status st = check_params(prm);
+    if (st != MPS_OK) return st;
+    if (!v || !ore_bits || !ton) return fail(MPS_E_INVALID_ARG, "v, ore_bits and ton are required");
+    int32_t ndev = 0;
+    if ((st = mps_device_count(&ndev)) != MPS_OK) return st;
+    if (!is_device_ptr(v) || !is_device_ptr(ore_bits) || !is_device_ptr(ton))
+        return fail(MPS_E_INVALID_ARG, "v, ore_bits and ton must be device pointers");
+    hipStream_t hs = (hipStream_t)stream;
+    if (capturing(hs)) return fail(MPS_E_NOT_CAPTURABLE, "mps_build_model during capture");
+
+    mps_model *m = new mps_model();
+    hipGetDevice(&m->device);
+    m->prm = *prm;
+    if (const char *lim = getenv("MPS_TEST_ALLOC_LIMIT")) m->limit = (size_t)strtoull(lim, 0, 10);
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device) ==
+            hipSuccess &&
+        lds > 0)
+        m->max_lds = lds;
+
+    DevModel &d = m->d;
+    d.nx = prm->nx;
+    d.ny = prm->ny;
+    d.nz = prm->nz;
+    d.N = (int64_t)prm->nx * prm->ny * prm->nz;
+    d.S = prm->n_scen;
+    d.T = prm->n_periods;
+    d.W = (d.S + 31) / 32;
+    d.lambda = prm->lambda;
+    d.pen_proc = prm->pen_proc;
+    d.pen_mine = prm->pen_mine;
+    d.pcap = prm->proc_cap;
+    d.mcap = prm->mine_cap;
+    const int64_t N = d.N;
+    const int32_t S = d.S, T = d.T, W = d.W;
+
+    // tonnages: validated and summarised on the host
+    std::vector<double> th((size_t)N);
+    hipError_t e = hipMemcpy(th.data(), ton, sizeof(double) * N, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        delete m;
+        return dev_fail(e, "copy of ton");
+    }
+    double tmin = INFINITY, tmax = 0.0;
+    for (int64_t b = 0; b < N; ++b) {
+        if (!(th[b] > 0.0) || !isfinite(th[b])) {
+            delete m;
+            return fail(MPS_E_INVALID_ARG, "ton[%lld] = %g must be finite and > 0", (long long)b,
+                        th[b]);
+        }
+        tmin = fmin(tmin, th[b]);
+        tmax = fmax(tmax, th[b]);
+    }
+    d.ton_min = tmin;
+    d.ton_max = tmax;
+
+    float *v_, *ton32, *mb32, *Vb32, *e32, *part_rem_a, *blk_c, *blk_rem;
+    uint32_t *ore_, *full_add, *full_rem;
+    double *ton64, *mb64, *Vb64, *Ns, *O, *M, *d64, *part_add_O;
+    int8_t *p;
+    int32_t *n_pa, *n_pr, *pa_s, *pr_s, *blk_info;
+    DevScalars *sc;
+#define ALLOC(ptr, cnt)                      \
+    if ((st = m->alloc(ptr, cnt)) != MPS_OK) { \
+        m->release();                        \
+        delete m;                            \
+        return st;                           \
+    }
+    ALLOC(v_, (size_t)S * N);
+    ALLOC(ore_, (size_t)W * N);
+    ALLOC(ton64, N);
+    ALLOC(ton32, N);
+    ALLOC(mb64, N);
+    ALLOC(Vb64, N);
+    ALLOC(mb32, N);
+    ALLOC(Vb32, N);
+    ALLOC(p, N);
+    ALLOC(Ns, S);
+    ALLOC(O, (size_t)T * S);
+    ALLOC(M, T);
+    ALLOC(e32, S);
+    ALLOC(sc, 1);
+    ALLOC(d64, T + 1);
+    ALLOC(full_add, (size_t)T * W);
+    ALLOC(full_rem, (size_t)T * W);
+    ALLOC(n_pa, T);
+    ALLOC(n_pr, T);
+    ALLOC(pa_s, (size_t)T * S);
+    ALLOC(part_add_O, (size_t)T * S);
+    ALLOC(pr_s, (size_t)T * S);
+    ALLOC(part_rem_a, (size_t)T * S);
+    ALLOC(blk_c, N);
+    ALLOC(blk_rem, N);
+    ALLOC(blk_info, N);
+    ALLOC(m->partial, (size_t)m->chunks * (S + 1) * (T + 1));
+    ALLOC(m->obj_dev, 8);
+#undef ALLOC
+    d.v = v_;
+    d.ore = ore_;
+    d.ton64 = ton64;
+    d.ton32 = ton32;
+    d.mb64 = mb64;
+    d.Vb64 = Vb64;
+    d.mb32 = mb32;
+    d.Vb32 = Vb32;
+    d.p = p;
+    d.Ns = Ns;
+    d.O = O;
+    d.M = M;
+    d.e32 = e32;
+    d.sc = sc;
+    d.d64 = d64;
+    d.tab.full_add = full_add;
+    d.tab.full_rem = full_rem;
+    d.tab.n_part_add = n_pa;
+    d.tab.n_part_rem = n_pr;
+    d.tab.part_add_s = pa_s;
+    d.tab.part_add_O = part_add_O;
+    d.tab.part_rem_s = pr_s;
+    d.tab.part_rem_a = part_rem_a;
+    d.blk_c = blk_c;
+    d.blk_rem = blk_rem;
+    d.blk_info = blk_info;
+
+    // discount factors: d(0) = 1, d(t) = d(t-1)/(1+rate), d(T) = 0
+    std::vector<double> dh((size_t)T + 1);
+    dh[0] = 1.0;
+    for (int32_t t = 1; t < T; ++t) dh[t] = dh[t - 1] / (1.0 + prm->discount_rate);
+    dh[T] = 0.0;
+    std::vector<float> t32((size_t)N);
+    for (int64_t b = 0; b < N; ++b) t32[b] = (float)th[b];
+
+    auto chk = [&](hipError_t err, const char *what) -> mps_status {
+        if (err == hipSuccess) return MPS_OK;
+        m->release();
+        delete m;
+        return dev_fail(err, what);
+    };
+    if ((st = chk(hipMemcpyAsync(v_, v, sizeof(float) * S * N, hipMemcpyDeviceToDevice, hs),
+                  "copy of v")) != MPS_OK)
+        return st;
+    if ((st = chk(hipMemcpyAsync(ore_, ore_bits, sizeof(uint32_t) * W * N,
+                                 hipMemcpyDeviceToDevice, hs),
+                  "copy of ore_bits")) != MPS_OK)
+        return st;
+    if ((st = chk(hipMemcpyAsync(ton64, ton, sizeof(double) * N, hipMemcpyDeviceToDevice, hs),
+                  "copy of ton")) != MPS_OK)
+        return st;
+    if ((st = chk(hipMemcpyAsync(ton32, t32.data(), sizeof(float) * N, hipMemcpyHostToDevice, hs),
+                  "copy of ton32")) != MPS_OK)
+        return st;
+    if ((st = chk(hipMemcpyAsync(d64, dh.data(), sizeof(double) * (T + 1),
+                                 hipMemcpyHostToDevice, hs),
+                  "copy of discount table")) != MPS_OK)
+        return st;
+    if ((st = chk(launch_block_stats(d, mb32, Vb32, mb64, Vb64, hs), "block statistics")) !=
+        MPS_OK)
+        return st;
+    // initial schedule: everything in period 0
+    std::vector<int8_t> zero((size_t)N, 0);
+    if ((st = chk(hipMemcpyAsync(p, zero.data(), N, hipMemcpyHostToDevice, hs), "schedule")) !=
+        MPS_OK)
+        return st;
+    if ((st = chk(launch_set_schedule(d, p, m->partial, m->chunks, hs), "set schedule")) != MPS_OK)
+        return st;
+    if ((st = chk(hipStreamSynchronize(hs), "build synchronise")) != MPS_OK) return st;
+    *out = m;
+    return MPS_OK;
+}
+
+mps_status mps_destroy_model(mps_model *m) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    DeviceGuard g(m->device);
+    hipDeviceSynchronize();
+    m->release();
+    delete m;
+    return MPS_OK;
+}
+
+mps_status mps_model_dims(const mps_model *m, int64_t *N, int32_t *S, int32_t *T) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    if (N) *N = m->d.N;
+    if (S) *S = m->d.S;
+    if (T) *T = m->d.T;
+    return MPS_OK;
+}
+
+mps_status mps_set_schedule(mps_model *m, const int8_t *p, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    if (!p) return fail(MPS_E_INVALID_ARG, "p is NULL");
+    DeviceGuard g(m->device);
+    hipError_t e = launch_set_schedule(m->d, p, m->partial, m->chunks, (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "set schedule");
+}
+
+mps_status mps_get_schedule(mps_model *m, int8_t *p, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    if (!p) return fail(MPS_E_INVALID_ARG, "p is NULL");
+    DeviceGuard g(m->device);
+    hipError_t e = hipMemcpyAsync(p, m->d.p, m->d.N, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "copy of schedule");
+}
+
+mps_status mps_objective_async(mps_model *m, double *out, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    if (!out) return fail(MPS_E_INVALID_ARG, "out is NULL");
+    DeviceGuard g(m->device);
+    hipError_t e = launch_objective_copy(m->d, out, (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "objective");
+}
+
+mps_status mps_get_objective(mps_model *m, mps_objective *out, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    if (!out) return fail(MPS_E_INVALID_ARG, "out is NULL");
+    hipStream_t hs = (hipStream_t)stream;
+    if (capturing(hs)) return fail(MPS_E_NOT_CAPTURABLE, "mps_get_objective during capture");
+    DeviceGuard g(m->device);
+    hipError_t e = launch_objective_copy(m->d, m->obj_dev, hs);
+    double h[7];
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h, m->obj_dev, sizeof(h), hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return dev_fail(e, "objective");
+    out->mu = h[0];
+    out->sigma = h[1];
+    out->R = h[2];
+    out->Pp = h[3];
+    out->Pm = h[4];
+    out->J = h[5];
+    out->n_prec_viol = (int64_t)h[6];
+    return MPS_OK;
+}
+
+static mps_status check_moves(const mps_model *m, const mps_moves *mv) {
+    if (!mv) return fail(MPS_E_INVALID_ARG, "moves is NULL");
+    if (mv->exhaustive) {
+        int32_t D = mv->include_never ? m->d.T + 1 : m->d.T;
+        if (m->d.N * (int64_t)D >= ((int64_t)1 << 31))
+            return fail(MPS_E_INVALID_ARG, "N*D = %lld moves exceed 2^31 - 1",
+                        (long long)(m->d.N * D));
+        return MPS_OK;
+    }
+    if (mv->n < 0 || mv->n >= ((int64_t)1 << 31))
+        return fail(MPS_E_INVALID_ARG, "moves->n = %lld out of range", (long long)mv->n);
+    if (mv->n > 0 && (!mv->block || !mv->period))
+        return fail(MPS_E_INVALID_ARG, "list moves need block and period arrays");
+    return MPS_OK;
+}
+
+mps_status mps_eval_moves(mps_model *m, const mps_moves *moves, float *score, uint8_t *flags,
+                          float *d_risk, float *d_pen_proc, float *d_pen_mine, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    mps_status st = check_moves(m, moves);
+    if (st != MPS_OK) return st;
+    if (!score || !flags) return fail(MPS_E_INVALID_ARG, "score and flags are required");
+    int nc = (d_risk != nullptr) + (d_pen_proc != nullptr) + (d_pen_mine != nullptr);
+    if (nc != 0 && nc != 3)
+        return fail(MPS_E_INVALID_ARG, "component outputs must be all given or all NULL");
+    DeviceGuard g(m->device);
+    hipError_t e = launch_eval(m->d, *moves, score, flags, d_risk, d_pen_proc, d_pen_mine,
+                               (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "eval moves");
+}
+
+size_t mps_topk_ws_bytes(int64_t n, int32_t k) {
+    if (k < 1) k = 1;
+    return topk_ws_bytes(n, k);
+}
+
+mps_status mps_topk(const float *score, const uint8_t *flags, int64_t n, int32_t k,
+                    uint8_t require, uint8_t forbid, int64_t *idx, float *top_score,
+                    int32_t *count, void *ws, size_t ws_bytes, void *stream) {
+    if (k < 1 || k > MPS_MAX_TOPK)
+        return fail(MPS_E_INVALID_ARG, "k must be in 1..%d (got %d)", MPS_MAX_TOPK, k);
+    if (n < 0 || n >= ((int64_t)1 << 31))
+        return fail(MPS_E_INVALID_ARG, "n = %lld out of range", (long long)n);
+    if ((n > 0 && (!score || !flags)) || !idx || !count || !ws)
+        return fail(MPS_E_INVALID_ARG, "score, flags, idx, count and ws are required");
+    if (ws_bytes < topk_ws_bytes(n, k))
+        return fail(MPS_E_INVALID_ARG, "workspace of %zu bytes is below the %zu needed", ws_bytes,
+                    topk_ws_bytes(n, k));
+    hipError_t e = launch_topk(score, flags, n, k, require, forbid, idx, top_score, count, ws,
+                               (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "topk");
+}
+
+mps_status mps_repair(mps_model *m, const mps_moves *moves, const int64_t *idx,
+                      const int32_t *count, int32_t max_cand, int32_t hard_capacity,
+                      int32_t *applied, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    mps_status st = check_moves(m, moves);
+    if (st != MPS_OK) return st;
+    if (!idx || !count) return fail(MPS_E_INVALID_ARG, "idx and count are required");
+    if (max_cand < 0 || max_cand > MPS_MAX_TOPK)
+        return fail(MPS_E_INVALID_ARG, "max_cand must be in 0..%d", MPS_MAX_TOPK);
+    size_t need = repair_lds_bytes(m->d, max_cand);
+    if (need > (size_t)m->max_lds)
+        return fail(MPS_E_INVALID_ARG,
+                    "repair state needs %zu bytes of LDS (S*T*8 + hash), device allows %d", need,
+                    m->max_lds);
+    DeviceGuard g(m->device);
+    hipError_t e = launch_repair(m->d, *moves, idx, count, max_cand, hard_capacity, applied,
+                                 (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "repair");
+}
+
+}  // extern "C"

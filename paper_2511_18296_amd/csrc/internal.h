@@ -1,0 +1,140 @@
+// internal.h -- device-side layout of a model and the launch helpers shared
+// by the HIP translation units of libmps.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mps.h"
+
+namespace mps {
+
+constexpr int kWave = 64;
+
+// Scalars derived from the per-scenario NPV vector; written by the state
+// kernels, read by every evaluation.
+struct DevScalars {
+    double mu, var, sigma;
+    double R, Pp, Pm, J;
+    double n_prec_viol;      // as double so the objective is one double[7]
+    float sigma32, var32;
+    int32_t n_bad_periods;   // schedule entries outside 0..T (clamped)
+    int32_t pad;
+};
+
+// Per-period tables of the processing-capacity penalty.  For period t and
+// scenario s with O = O[t][s] (FP64) and a = O - proc_cap:
+//   add term (block b moved INTO t):  hinge(O + ton_b) - hinge(O)
+//     full    : O >= cap and O + ton_min > cap  -> value ton_b, always a
+//               capacity violation
+//     partial : otherwise, if O + ton_max > cap -> evaluated per block in
+//               FP64 (value and violation)
+//     none    : O + ton_max <= cap              -> 0, never a violation
+//   removal term (block b moved OUT of t): hinge(O - ton_b) - hinge(O)
+//     = -clamp(a, 0, ton_b): full (-ton_b) when a >= ton_max, zero when
+//     a <= 0, partial (-min(a, ton_b)) otherwise.
+struct PeriodTables {
+    uint32_t *full_add;    // [T][W] bit s%32 of word s/32
+    uint32_t *full_rem;    // [T][W]
+    int32_t *n_part_add;   // [T]
+    int32_t *n_part_rem;   // [T]
+    int32_t *part_add_s;   // [T][S] scenario ids, ascending
+    double *part_add_O;    // [T][S] O[t][s] of those scenarios
+    int32_t *part_rem_s;   // [T][S]
+    float *part_rem_a;     // [T][S] O[t][s] - cap of those scenarios
+};
+
+struct DevModel {
+    int64_t N;
+    int32_t S, T, W, nx, ny, nz;
+    double lambda, pen_proc, pen_mine, pcap, mcap;
+    double ton_min, ton_max;
+    const float *v;        // [S][N]
+    const uint32_t *ore;   // [W][N]
+    const double *ton64;   // [N]
+    const float *ton32;    // [N]
+    const double *mb64;    // [N] mean_s v[s][b]
+    const double *Vb64;    // [N] population variance_s v[s][b]
+    const float *mb32;
+    const float *Vb32;
+    int8_t *p;             // [N] current schedule
+    double *Ns;            // [S] per-scenario NPV
+    double *O;             // [T][S] ore tonnage per period and scenario
+    double *M;             // [T] tonnage per period
+    float *e32;            // [S] N_s - mu
+    DevScalars *sc;
+    const double *d64;     // [T+1] discount factors, d[T] = 0
+    PeriodTables tab;
+    // list-mode per-block workspace
+    float *blk_c;          // [N] (1/S) sum_s e_s v[s][b]
+    float *blk_rem;        // [N] sum_s ore (removal clamp) for the current period
+    int32_t *blk_info;     // [N] p | maxPred << 8 | minSucc << 16
+};
+
+// Launch wrappers (each returns the hipError_t of its launches).
+hipError_t launch_block_stats(const DevModel &m, float *mb32, float *Vb32,
+                              double *mb64, double *Vb64, hipStream_t st);
+hipError_t launch_set_schedule(const DevModel &m, const int8_t *p_in,
+                               double *partial, int chunks, hipStream_t st);
+hipError_t launch_prep(const DevModel &m, hipStream_t st);
+hipError_t launch_objective_copy(const DevModel &m, double *out, hipStream_t st);
+hipError_t launch_eval(const DevModel &m, const mps_moves &mv, float *score,
+                       uint8_t *flags, float *dR, float *dPp, float *dPm,
+                       hipStream_t st);
+size_t topk_ws_bytes(int64_t n, int32_t k);
+hipError_t launch_topk(const float *score, const uint8_t *flags, int64_t n,
+                       int32_t k, uint8_t req, uint8_t forbid, int64_t *idx,
+                       float *top_score, int32_t *count, void *ws,
+                       hipStream_t st);
+size_t repair_lds_bytes(const DevModel &m, int32_t max_cand);
+hipError_t launch_repair(const DevModel &m, const mps_moves &mv,
+                         const int64_t *idx, const int32_t *count,
+                         int32_t max_cand, int32_t hard, int32_t *applied,
+                         hipStream_t st);
+
+// Precedence neighbours under the 1-5 stencil; shared by the kernels.
+__device__ __forceinline__ void grid_coords(const DevModel &m, int32_t b,
+                                            int32_t &x, int32_t &y, int32_t &z) {
+    int32_t nxy = m.nx * m.ny;
+    z = b / nxy;
+    int32_t r = b - z * nxy;
+    y = r / m.nx;
+    x = r - y * m.nx;
+}
+
+// max over predecessors of p (0 if none) and min over successors (T if none),
+// the two numbers that decide PREC_OK for every destination of b.
+__device__ __forceinline__ void prec_window(const DevModel &m, const int8_t *p,
+                                            int32_t b, int32_t &lo, int32_t &hi) {
+    int32_t x, y, z;
+    grid_coords(m, b, x, y, z);
+    const int32_t nx = m.nx, nxy = m.nx * m.ny, T = m.T;
+    lo = 0;
+    hi = T;
+    auto rd = [&](int32_t a) {
+        int32_t v = p[a];
+        return (v < 0 || v > T) ? T : v;
+    };
+    if (z > 0) {
+        int32_t a = b - nxy;
+        lo = max(lo, rd(a));
+        if (x > 0) lo = max(lo, rd(a - 1));
+        if (x + 1 < nx) lo = max(lo, rd(a + 1));
+        if (y > 0) lo = max(lo, rd(a - nx));
+        if (y + 1 < m.ny) lo = max(lo, rd(a + nx));
+    }
+    if (z + 1 < m.nz) {
+        int32_t c = b + nxy;
+        hi = min(hi, rd(c));
+        if (x > 0) hi = min(hi, rd(c - 1));
+        if (x + 1 < nx) hi = min(hi, rd(c + 1));
+        if (y > 0) hi = min(hi, rd(c - nx));
+        if (y + 1 < m.ny) hi = min(hi, rd(c + nx));
+    }
+}
+
+__device__ __forceinline__ double hinge64(double x, double cap) {
+    return x > cap ? x - cap : 0.0;
+}
+
+}  // namespace mps

@@ -1,0 +1,287 @@
+// state.hip -- per-block statistics, schedule state and penalty tables.
+//
+// State of a schedule p (Sec. 5, Eq. 14 and 16):
+//   N_s = sum_b v[s][b] d(p_b)           (FP64)
+//   O[t][s] = sum_{b: p_b = t} ton_b ore[s][b],  M[t] = sum_{b: p_b=t} ton_b
+// Every reduction has a fixed order (per-thread strided partial sums, then a
+// fixed tree), so results are bit-reproducible run to run.
+#include "internal.h"
+
+namespace mps {
+
+// ---- per-block mean and variance over scenarios (two-pass, FP64) ----------
+__global__ void k_block_stats(DevModel m, float *mb32, float *Vb32, double *mb64,
+                              double *Vb64) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= m.N) return;
+    double s1 = 0.0;
+    for (int32_t s = 0; s < m.S; ++s) s1 += (double)m.v[(int64_t)s * m.N + b];
+    double mu = s1 / m.S;
+    double s2 = 0.0;
+    for (int32_t s = 0; s < m.S; ++s) {
+        double e = (double)m.v[(int64_t)s * m.N + b] - mu;
+        s2 += e * e;
+    }
+    double var = s2 / m.S;
+    mb64[b] = mu;
+    Vb64[b] = var;
+    mb32[b] = (float)mu;
+    Vb32[b] = (float)var;
+}
+
+hipError_t launch_block_stats(const DevModel &m, float *mb32, float *Vb32,
+                              double *mb64, double *Vb64, hipStream_t st) {
+    int64_t grid = (m.N + 255) / 256;
+    hipLaunchKernelGGL(k_block_stats, dim3((unsigned)grid), dim3(256), 0, st, m,
+                       mb32, Vb32, mb64, Vb64);
+    return hipGetLastError();
+}
+
+// ---- schedule state --------------------------------------------------------
+// Copy p into the model, clamping values outside 0..T to T (never mined).
+__global__ void k_copy_schedule(DevModel m, const int8_t *p_in) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= m.N) return;
+    int32_t t = p_in[b];
+    m.p[b] = (int8_t)((t < 0 || t > m.T) ? m.T : t);
+}
+
+// Partial sums over one chunk of blocks.  Row r < S: N_s and O[.][s] for
+// scenario s = r; row r == S: M[.], precedence violations and clamped
+// entries.  64 threads; each keeps private per-period accumulators in LDS.
+// partial layout: [chunk][S+1][T+1]  (entry T of a scenario row holds N_s,
+// entry T of the last row the violation count).
+__global__ void __launch_bounds__(64) k_state_partial(DevModel m, const int8_t *p_in,
+                                                      double *partial, int chunks) {
+    extern __shared__ double acc[];   // [T][64]
+    const int tid = threadIdx.x;
+    const int ch = blockIdx.x;
+    const int r = blockIdx.y;
+    const int32_t T = m.T;
+    for (int t = 0; t < T; ++t) acc[t * 64 + tid] = 0.0;
+    int64_t per = (m.N + chunks - 1) / chunks;
+    int64_t b0 = (int64_t)ch * per, b1 = min(m.N, b0 + per);
+    double nacc = 0.0;
+    if (r < m.S) {
+        const int32_t s = r;
+        const float *vrow = m.v + (int64_t)s * m.N;
+        const uint32_t *orow = m.ore + (int64_t)(s >> 5) * m.N;
+        const uint32_t bit = 1u << (s & 31);
+        for (int64_t b = b0 + tid; b < b1; b += 64) {
+            int32_t t = p_in[b];
+            if (t < 0 || t > T) t = T;
+            nacc += (double)vrow[b] * m.d64[t];
+            if (t < T && (orow[b] & bit)) acc[t * 64 + tid] += m.ton64[b];
+        }
+    } else {
+        for (int64_t b = b0 + tid; b < b1; b += 64) {
+            int32_t t = p_in[b];
+            bool bad = (t < 0 || t > T);
+            if (bad) t = T;
+            if (t < T) acc[t * 64 + tid] += m.ton64[b];
+            // predecessor pairs with p[a] > p[b]
+            int32_t x, y, z;
+            grid_coords(m, (int32_t)b, x, y, z);
+            double nv = bad ? 1.0 : 0.0;
+            if (z > 0) {
+                const int32_t nxy = m.nx * m.ny;
+                int64_t a = b - nxy;
+                auto pa = [&](int64_t i) {
+                    int32_t u = p_in[i];
+                    return (u < 0 || u > T) ? T : u;
+                };
+                if (pa(a) > t) nv += 1.0;
+                if (x > 0 && pa(a - 1) > t) nv += 1.0;
+                if (x + 1 < m.nx && pa(a + 1) > t) nv += 1.0;
+                if (y > 0 && pa(a - m.nx) > t) nv += 1.0;
+                if (y + 1 < m.ny && pa(a + m.nx) > t) nv += 1.0;
+            }
+            nacc += nv;
+        }
+    }
+    __syncthreads();
+    double *out = partial + ((int64_t)ch * (m.S + 1) + r) * (T + 1);
+    for (int t = tid; t < T; t += 64) {
+        double s = 0.0;
+        for (int j = 0; j < 64; ++j) s += acc[t * 64 + j];
+        out[t] = s;
+    }
+    // fixed-order tree over the 64 lanes for the scalar accumulator
+    __syncthreads();
+    acc[tid] = nacc;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (tid < w) acc[tid] += acc[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) out[T] = acc[0];
+}
+
+// Sum the chunk partials in chunk order into N_s, O, M and the counts.
+__global__ void k_state_finish(DevModel m, const double *partial, int chunks) {
+    const int32_t S = m.S, T = m.T;
+    int64_t n = (int64_t)(S + 1) * (T + 1);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < chunks; ++c) s += partial[(int64_t)c * n + i];
+        int32_t r = (int32_t)(i / (T + 1)), t = (int32_t)(i % (T + 1));
+        if (r < S) {
+            if (t < T) m.O[(int64_t)t * S + r] = s;
+            else m.Ns[r] = s;
+        } else {
+            if (t < T) m.M[t] = s;
+            else m.sc->n_prec_viol = s;
+        }
+    }
+}
+
+hipError_t launch_set_schedule(const DevModel &m, const int8_t *p_in,
+                               double *partial, int chunks, hipStream_t st) {
+    int64_t g = (m.N + 255) / 256;
+    hipLaunchKernelGGL(k_copy_schedule, dim3((unsigned)g), dim3(256), 0, st, m, p_in);
+    size_t lds = (size_t)m.T * 64 * sizeof(double);
+    if (lds < 64 * sizeof(double)) lds = 64 * sizeof(double);
+    hipLaunchKernelGGL(k_state_partial, dim3(chunks, m.S + 1), dim3(64), lds, st, m,
+                       p_in, partial, chunks);
+    hipLaunchKernelGGL(k_state_finish, dim3(64), dim3(256), 0, st, m, partial, chunks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_prep(m, st);
+}
+
+// ---- statistics and penalty tables from (N_s, O, M) ------------------------
+__device__ double block_sum_f64(double x, double *red) {
+    // fixed-order tree over blockDim.x (power of two) threads
+    const int tid = threadIdx.x;
+    __syncthreads();
+    red[tid] = x;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Block T: mu, var, sigma, e_s and the objective terms.  Blocks t < T: the
+// penalty tables of period t.  256 threads.
+__global__ void __launch_bounds__(256) k_prep(DevModel m) {
+    __shared__ double red[256];
+    __shared__ int32_t woff[4];
+    const int tid = threadIdx.x;
+    const int32_t S = m.S, T = m.T, W = m.W;
+    const int32_t t = blockIdx.x;
+    if (t == T) {
+        double s = 0.0;
+        for (int32_t i = tid; i < S; i += 256) s += m.Ns[i];
+        double mu = block_sum_f64(s, red) / S;
+        double q = 0.0;
+        for (int32_t i = tid; i < S; i += 256) {
+            double e = m.Ns[i] - mu;
+            q += e * e;
+        }
+        double var = block_sum_f64(q, red) / S;
+        double pp = 0.0;
+        for (int64_t i = tid; i < (int64_t)S * T; i += 256) pp += hinge64(m.O[i], m.pcap);
+        pp = block_sum_f64(pp, red);
+        for (int32_t i = tid; i < S; i += 256) m.e32[i] = (float)(m.Ns[i] - mu);
+        if (tid == 0) {
+            double pm = 0.0;
+            for (int32_t u = 0; u < T; ++u) pm += hinge64(m.M[u], m.mcap);
+            double sigma = sqrt(var);
+            DevScalars *sc = m.sc;
+            sc->mu = mu;
+            sc->var = var;
+            sc->sigma = sigma;
+            sc->sigma32 = (float)sigma;
+            sc->var32 = (float)var;
+            sc->R = mu - m.lambda * sigma;
+            sc->Pp = m.pen_proc * pp / S;
+            sc->Pm = m.pen_mine * pm;
+            sc->J = sc->R - sc->Pp - sc->Pm;
+        }
+        return;
+    }
+    // tables of period t
+    const int lane = tid & 63, wave = tid >> 6;
+    int32_t base_add = 0, base_rem = 0;
+    for (int32_t s0 = 0; s0 < S; s0 += 256) {
+        int32_t s = s0 + tid;
+        bool in = s < S;
+        double O = in ? m.O[(int64_t)t * S + s] : 0.0;
+        bool full_add = in && O >= m.pcap && O + m.ton_min > m.pcap;
+        bool part_add = in && !full_add && O + m.ton_max > m.pcap;
+        double a = O - m.pcap;
+        bool full_rem = in && a >= m.ton_max;
+        bool part_rem = in && !full_rem && a > 0.0;
+        uint64_t bfa = __ballot(full_add), bfr = __ballot(full_rem);
+        uint64_t bpa = __ballot(part_add), bpr = __ballot(part_rem);
+        if (lane == 0) {
+            int32_t w0 = (s0 >> 5) + wave * 2;   // 64 scenarios = 2 words
+            if (w0 < W) {
+                m.tab.full_add[(int64_t)t * W + w0] = (uint32_t)bfa;
+                m.tab.full_rem[(int64_t)t * W + w0] = (uint32_t)bfr;
+            }
+            if (w0 + 1 < W) {
+                m.tab.full_add[(int64_t)t * W + w0 + 1] = (uint32_t)(bfa >> 32);
+                m.tab.full_rem[(int64_t)t * W + w0 + 1] = (uint32_t)(bfr >> 32);
+            }
+        }
+        // order-preserving compaction of the partial scenarios
+        __syncthreads();
+        if (lane == 0) woff[wave] = (int32_t)__popcll(bpa) | ((int32_t)__popcll(bpr) << 16);
+        __syncthreads();
+        int32_t oa = base_add, orr = base_rem, ta = 0, tr = 0;
+        for (int w = 0; w < 4; ++w) {
+            int32_t ca = woff[w] & 0xffff, cr = woff[w] >> 16;
+            if (w < wave) { oa += ca; orr += cr; }
+            ta += ca;
+            tr += cr;
+        }
+        uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        if (part_add) {
+            int32_t j = oa + (int32_t)__popcll(bpa & below);
+            m.tab.part_add_s[(int64_t)t * S + j] = s;
+            m.tab.part_add_O[(int64_t)t * S + j] = O;
+        }
+        if (part_rem) {
+            int32_t j = orr + (int32_t)__popcll(bpr & below);
+            m.tab.part_rem_s[(int64_t)t * S + j] = s;
+            m.tab.part_rem_a[(int64_t)t * S + j] = (float)a;
+        }
+        base_add += ta;
+        base_rem += tr;
+    }
+    if (tid == 0) {
+        m.tab.n_part_add[t] = base_add;
+        m.tab.n_part_rem[t] = base_rem;
+    }
+}
+
+hipError_t launch_prep(const DevModel &m, hipStream_t st) {
+    hipLaunchKernelGGL(k_prep, dim3(m.T + 1), dim3(256), 0, st, m);
+    return hipGetLastError();
+}
+
+__global__ void k_objective_copy(DevModel m, double *out) {
+    if (threadIdx.x == 0) {
+        const DevScalars *sc = m.sc;
+        out[0] = sc->mu;
+        out[1] = sc->sigma;
+        out[2] = sc->R;
+        out[3] = sc->Pp;
+        out[4] = sc->Pm;
+        out[5] = sc->J;
+        out[6] = sc->n_prec_viol;
+    }
+}
+
+hipError_t launch_objective_copy(const DevModel &m, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_objective_copy, dim3(1), dim3(64), 0, st, m, out);
+    return hipGetLastError();
+}
+
+}  // namespace mps

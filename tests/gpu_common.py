@@ -1,0 +1,54 @@
+"""Helpers shared by the GPU tests (instances, oracle runs, comparisons)."""
+import functools
+
+import numpy as np
+import torch
+
+import mpsgen
+import oracle
+
+# Contract: float deltas within 1e-5 of |expected NPV| of the schedule.
+CONTRACT_REL = 1e-5
+
+
+@functools.lru_cache(maxsize=None)
+def instance(name):
+    if name == "tiny":
+        return mpsgen.tiny_plain()
+    if name == "paper":
+        return mpsgen.paper_scale()
+    if name == "largest":
+        return mpsgen.largest_plain()
+    if name == "ragged":
+        # N, S, T that fill no tile, word or wave evenly
+        return mpsgen.make_instance(7, 5, 3, 37, 3, 1.5, 77)
+    if name == "flat":
+        # one bench: no precedence at all
+        return mpsgen.make_instance(13, 11, 1, 65, 4, 2.0, 78)
+    if name == "single":
+        return mpsgen.make_instance(6, 6, 4, 1, 6, 2.0, 79)
+    if name == "tight":
+        inst = mpsgen.make_instance(12, 10, 6, 96, 8, 2.0, 80)
+        inst.pcap *= 0.85        # capacities bind in most periods
+        inst.mcap *= 0.8
+        return inst
+    raise KeyError(name)
+
+
+def gpu_model(inst):
+    from paper_2511_18296_amd.binding import Model
+    return Model.from_instance(inst, device="cuda")
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def compare_scores(gpu_score, ora_score, flags, mu, label=""):
+    """Max |gpu - oracle| over non-BAD moves; asserts the contract bound."""
+    ok = (flags & oracle.BAD) == 0
+    err = np.abs(gpu_score[ok].astype(np.float64) - ora_score[ok])
+    mx = float(err.max()) if err.size else 0.0
+    bound = CONTRACT_REL * abs(mu)
+    assert mx <= bound, f"{label}: max |score err| {mx:.4g} > {bound:.4g}"
+    return mx
