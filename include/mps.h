@@ -189,6 +189,71 @@ mps_status mps_repair(mps_model *m, const mps_moves *moves,
                       int32_t max_cand, int32_t hard_capacity,
                       int32_t *applied, void *stream);
 
+/* ---- relaxed, differentiable schedule ------------------------------------
+ * x (device float [N][T]) is the cumulative fraction of each block mined by
+ * the end of each period, y[b,t] = x[b,t] - x[b,t-1] (x[b,-1] = 0); the caller
+ * keeps x in [0,1] and non-decreasing in t.  The relaxed objective is the
+ * risk-adjusted expectation of Eq. 14 on the relaxed plan with quadratic
+ * penalties for the capacities (Eq. 16 and the plant) and for precedence
+ * (Eq. 15):
+ *   NPV_s = sum_b v[s][b] sum_t d(t) y[b,t];  mu, sigma over s
+ *   Ot[s,t] = sum_b ton_b ore[s][b] y[b,t],  Mt[t] = sum_b ton_b y[b,t]
+ *   J = mu - lambda*sigma - (mu_proc/S) sum_{s,t} max(0, Ot - proc_cap)^2
+ *       - mu_mine sum_t max(0, Mt - mine_cap)^2
+ *       - mu_prec sum_b sum_{a in Pred(b)} sum_t max(0, x[b,t] - x[a,t])^2
+ * At an integer point x[b,t] = [t >= p_b] of a feasible schedule with
+ * mu_proc = mu_mine = 0, J equals mu - lambda*sigma of mps_get_objective. */
+
+/* Device bytes of the state the forward pass saves for the backward pass. */
+size_t mps_relaxed_saved_bytes(const mps_model *m);
+
+/* Forward: J_out (device double[6] or NULL) = J, mu, sigma, proc penalty,
+ * mining penalty, precedence penalty; `saved` (device, caller-owned,
+ * mps_relaxed_saved_bytes) receives what the backward pass needs.  Uses the
+ * model's workspace: calls on one model must not overlap. */
+mps_status mps_relaxed_fwd(mps_model *m, const float *x, const mps_relax_params *rp,
+                           double *J_out, void *saved, void *stream);
+
+/* Adjoint: grad_x (device float [N][T]) = dJ * dJ/dx at x, from the state a
+ * forward call at the same x saved.  dJ: device double scalar, or NULL for 1.
+ * The derivative of sigma uses w_s = 1/S - lambda (NPV_s - mu)/(S sigma), and
+ * 1/S when sigma <= 1e-12 * max(1, |mu|). */
+mps_status mps_relaxed_bwd(mps_model *m, const float *x, const mps_relax_params *rp,
+                           const void *saved, const double *dJ, float *grad_x,
+                           void *stream);
+
+/* Workspace bytes of mps_rank_moves for k moves. */
+size_t mps_rank_ws_bytes(const mps_model *m, int32_t k);
+
+/* Gradient ranking of every non-no-op move (b, t') against the current
+ * schedule: gain = Gc[b][p_b] - Gc[b][t'] with Gc[b][t] = sum_{u<t} grad_x[b][u]
+ * (the first-order change of J along x(p') - x(p)); returns the k best
+ * (gain descending, move index b*(T+1)+t' ascending) as block (int32 [k]),
+ * period (int8 [k]), gain (float [k], may be NULL) and *count (device int32);
+ * entries past the count are -1.  1 <= k <= MPS_MAX_TOPK. */
+mps_status mps_rank_moves(mps_model *m, const float *grad_x, int32_t k, int32_t *block,
+                          int8_t *period, float *gain, int32_t *count, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Search loops from the current schedule (the repair-driven local search the
+ * paper's Alg. 2 and 4 run around the GPU evaluation):
+ *   mode 0 (exhaustive): repeat { evaluate all N(T+1) moves, top k, repair }
+ *     until a repair applies nothing;
+ *   mode 1 (gradient-ranked): repeat { relaxed gradient at x(p), rank all
+ *     moves, evaluate the top k exactly, top k, repair }; when a round applies
+ *     nothing, one exhaustive round certifies (and the loop continues if it
+ *     applied something).
+ * ALLOCATES its buffers and SYNCHRONISES every round (not capturable). */
+typedef struct {
+    int64_t iterations;    /* rounds run */
+    int64_t evaluations;   /* moves evaluated exactly (eval calls) */
+    int64_t applied;       /* moves applied */
+    double J;              /* objective of the final schedule */
+} mps_search_stats;
+
+mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_params *rp,
+                      int32_t max_iter, mps_search_stats *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

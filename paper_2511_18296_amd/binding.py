@@ -54,6 +54,11 @@ class RelaxParams(C.Structure):
                 ("mu_prec", C.c_double)]
 
 
+class SearchStats(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("evaluations", C.c_int64),
+                ("applied", C.c_int64), ("J", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -76,6 +81,12 @@ def _load():
         "mps_topk": ([vp, vp, i64, i32, C.c_uint8, C.c_uint8, vp, vp, vp, vp,
                       C.c_size_t, vp], st),
         "mps_repair": ([vp, vp, vp, vp, i32, i32, vp, vp], st),
+        "mps_relaxed_saved_bytes": ([vp], C.c_size_t),
+        "mps_relaxed_fwd": ([vp, vp, vp, vp, vp, vp], st),
+        "mps_relaxed_bwd": ([vp, vp, vp, vp, vp, vp, vp], st),
+        "mps_rank_ws_bytes": ([vp, i32], C.c_size_t),
+        "mps_rank_moves": ([vp, vp, i32, vp, vp, vp, vp, vp, C.c_size_t, vp], st),
+        "mps_search": ([vp, i32, i32, vp, i32, vp, vp], st),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -90,7 +101,9 @@ lib = _load()
 EXPORTS = ("mps_last_error", "mps_version", "mps_device_count", "mps_build_model",
            "mps_destroy_model", "mps_model_dims", "mps_set_schedule",
            "mps_get_schedule", "mps_get_objective", "mps_objective_async",
-           "mps_eval_moves", "mps_topk_ws_bytes", "mps_topk", "mps_repair")
+           "mps_eval_moves", "mps_topk_ws_bytes", "mps_topk", "mps_repair",
+           "mps_relaxed_saved_bytes", "mps_relaxed_fwd", "mps_relaxed_bwd",
+           "mps_rank_ws_bytes", "mps_rank_moves", "mps_search")
 
 
 def check(status: int):
@@ -243,6 +256,75 @@ class Model:
         check(lib.mps_repair(self.h, C.byref(mv), _ptr(idx), _ptr(count), int(max_cand),
                              int(bool(hard)), _ptr(applied), _stream(stream)))
         return applied
+
+
+    # ---- relaxed objective -------------------------------------------------
+    def relaxed_saved(self):
+        n = int(lib.mps_relaxed_saved_bytes(self.h))
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def relaxed_fwd(self, x, relax, saved, J_out=None, stream=None):
+        _dev(x, torch.float32, (self.N, self.T), "x")
+        rp = RelaxParams(*relax)
+        if J_out is None:
+            J_out = torch.empty(6, dtype=torch.float64, device=self.device)
+        check(lib.mps_relaxed_fwd(self.h, _ptr(x), C.byref(rp), _ptr(J_out), _ptr(saved),
+                                  _stream(stream)))
+        return J_out
+
+    def relaxed_bwd(self, x, relax, saved, dJ=None, grad=None, stream=None):
+        _dev(x, torch.float32, (self.N, self.T), "x")
+        rp = RelaxParams(*relax)
+        if grad is None:
+            grad = torch.empty_like(x)
+        if dJ is not None:
+            _dev(dJ, torch.float64, None, "dJ")
+        check(lib.mps_relaxed_bwd(self.h, _ptr(x), C.byref(rp), _ptr(saved), _ptr(dJ),
+                                  _ptr(grad), _stream(stream)))
+        return grad
+
+    def rank_moves(self, grad, k, stream=None):
+        _dev(grad, torch.float32, (self.N, self.T), "grad")
+        nb = int(lib.mps_rank_ws_bytes(self.h, int(k)))
+        ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        blk = torch.empty(k, dtype=torch.int32, device=self.device)
+        per = torch.empty(k, dtype=torch.int8, device=self.device)
+        gain = torch.empty(k, dtype=torch.float32, device=self.device)
+        cnt = torch.zeros(1, dtype=torch.int32, device=self.device)
+        check(lib.mps_rank_moves(self.h, _ptr(grad), int(k), _ptr(blk), _ptr(per), _ptr(gain),
+                                 _ptr(cnt), _ptr(ws), nb, _stream(stream)))
+        return blk, per, gain, cnt
+
+    def search(self, mode, k, relax=(0.0, 0.0, 0.0), max_iter=1000, stream=None) -> dict:
+        rp = RelaxParams(*relax)
+        st = SearchStats()
+        check(lib.mps_search(self.h, int(mode), int(k), C.byref(rp), int(max_iter),
+                             C.byref(st), _stream(stream)))
+        return dict(iterations=st.iterations, evaluations=st.evaluations,
+                    applied=st.applied, J=st.J)
+
+
+class RelaxedNPV(torch.autograd.Function):
+    """J(x) of the relaxed schedule, with the hand-written adjoint as backward.
+
+    J = RelaxedNPV.apply(x, model, (mu_proc, mu_mine, mu_prec)) returns a
+    float64 scalar on the GPU; J.backward() fills x.grad through
+    mps_relaxed_bwd on the current stream."""
+
+    @staticmethod
+    def forward(ctx, x, model, relax):
+        saved = model.relaxed_saved()
+        Jv = model.relaxed_fwd(x.detach(), relax, saved)
+        ctx.model, ctx.relax = model, relax
+        ctx.save_for_backward(x, saved)
+        return Jv[0].clone()
+
+    @staticmethod
+    def backward(ctx, gJ):
+        x, saved = ctx.saved_tensors
+        dJ = gJ.detach().to(torch.float64).reshape(1).contiguous()
+        g = ctx.model.relaxed_bwd(x.detach(), ctx.relax, saved, dJ=dJ)
+        return g, None, None
 
 
 class TopK:

@@ -61,6 +61,24 @@ bool is_device_ptr(const void *p) {
     return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
+// Device buffers owned by one mps_search call.
+struct SearchBufs {
+    std::vector<void *> ptrs;
+    ~SearchBufs() {
+        for (void *p : ptrs) hipFree(p);
+    }
+    template <class T>
+    T *get(size_t count) {
+        void *p = nullptr;
+        if (hipMalloc(&p, sizeof(T) * (count > 0 ? count : 1)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        ptrs.push_back(p);
+        return (T *)p;
+    }
+};
+
 }  // namespace
 
 struct mps_model {
@@ -73,6 +91,7 @@ struct mps_model {
     double *partial = nullptr;
     int chunks = 8;
     double *obj_dev = nullptr;   // double[7]
+    void *relax_ws = nullptr;    // partial sums of the relaxed forward pass
     int max_lds = 65536;
 
     template <class T>
@@ -243,6 +262,11 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     ALLOC(blk_info, N);
     ALLOC(m->partial, (size_t)m->chunks * (S + 1) * (T + 1));
     ALLOC(m->obj_dev, 8);
+    {
+        char *rw = nullptr;
+        ALLOC(rw, relaxed_ws_bytes(d));
+        m->relax_ws = rw;
+    }
 #undef ALLOC
     d.v = v_;
     d.ore = ore_;
@@ -401,6 +425,10 @@ mps_status mps_eval_moves(mps_model *m, const mps_moves *moves, float *score, ui
     if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
     mps_status st = check_moves(m, moves);
     if (st != MPS_OK) return st;
+    const int64_t n_moves =
+        moves->exhaustive ? m->d.N * (int64_t)(moves->include_never ? m->d.T + 1 : m->d.T)
+                          : moves->n;
+    if (n_moves == 0) return MPS_OK;
     if (!score || !flags) return fail(MPS_E_INVALID_ARG, "score and flags are required");
     int nc = (d_risk != nullptr) + (d_pen_proc != nullptr) + (d_pen_mine != nullptr);
     if (nc != 0 && nc != 3)
@@ -451,6 +479,166 @@ mps_status mps_repair(mps_model *m, const mps_moves *moves, const int64_t *idx,
     hipError_t e = launch_repair(m->d, *moves, idx, count, max_cand, hard_capacity, applied,
                                  (hipStream_t)stream);
     return e == hipSuccess ? MPS_OK : dev_fail(e, "repair");
+}
+
+size_t mps_relaxed_saved_bytes(const mps_model *m) {
+    return m ? relaxed_saved_bytes(m->d) : 0;
+}
+
+static mps_status check_relax(const mps_relax_params *rp) {
+    if (!rp) return fail(MPS_E_INVALID_ARG, "relax params are NULL");
+    if (!isfinite(rp->mu_proc) || !isfinite(rp->mu_mine) || !isfinite(rp->mu_prec) ||
+        rp->mu_proc < 0 || rp->mu_mine < 0 || rp->mu_prec < 0)
+        return fail(MPS_E_INVALID_ARG, "relaxed penalty weights must be finite and >= 0");
+    return MPS_OK;
+}
+
+mps_status mps_relaxed_fwd(mps_model *m, const float *x, const mps_relax_params *rp,
+                           double *J_out, void *saved, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    mps_status st = check_relax(rp);
+    if (st != MPS_OK) return st;
+    if (!x || !saved) return fail(MPS_E_INVALID_ARG, "x and saved are required");
+    DeviceGuard g(m->device);
+    hipError_t e = launch_relaxed_fwd(m->d, x, *rp, J_out, saved, m->relax_ws, (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "relaxed forward");
+}
+
+mps_status mps_relaxed_bwd(mps_model *m, const float *x, const mps_relax_params *rp,
+                           const void *saved, const double *dJ, float *grad_x, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    mps_status st = check_relax(rp);
+    if (st != MPS_OK) return st;
+    if (!x || !saved || !grad_x) return fail(MPS_E_INVALID_ARG, "x, saved and grad_x are required");
+    DeviceGuard g(m->device);
+    hipError_t e = launch_relaxed_bwd(m->d, x, *rp, saved, dJ, grad_x, (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "relaxed backward");
+}
+
+size_t mps_rank_ws_bytes(const mps_model *m, int32_t k) {
+    if (!m) return 0;
+    if (k < 1) k = 1;
+    return rank_ws_bytes(m->d, k);
+}
+
+mps_status mps_rank_moves(mps_model *m, const float *grad_x, int32_t k, int32_t *block,
+                          int8_t *period, float *gain, int32_t *count, void *ws,
+                          size_t ws_bytes, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    if (k < 1 || k > MPS_MAX_TOPK)
+        return fail(MPS_E_INVALID_ARG, "k must be in 1..%d (got %d)", MPS_MAX_TOPK, k);
+    if (!grad_x || !block || !period || !count || !ws)
+        return fail(MPS_E_INVALID_ARG, "grad_x, block, period, count and ws are required");
+    if (m->d.N * (int64_t)(m->d.T + 1) >= ((int64_t)1 << 31))
+        return fail(MPS_E_INVALID_ARG, "too many moves to rank");
+    if (ws_bytes < rank_ws_bytes(m->d, k))
+        return fail(MPS_E_INVALID_ARG, "workspace of %zu bytes is below the %zu needed", ws_bytes,
+                    rank_ws_bytes(m->d, k));
+    DeviceGuard g(m->device);
+    hipError_t e = launch_rank(m->d, grad_x, k, block, period, gain, count, ws, (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "rank moves");
+}
+
+mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_params *rp,
+                      int32_t max_iter, mps_search_stats *out, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    if (mode != 0 && mode != 1) return fail(MPS_E_INVALID_ARG, "mode must be 0 or 1");
+    if (k < 1 || k > MPS_MAX_TOPK)
+        return fail(MPS_E_INVALID_ARG, "k must be in 1..%d (got %d)", MPS_MAX_TOPK, k);
+    if (max_iter < 0) return fail(MPS_E_INVALID_ARG, "max_iter must be >= 0");
+    mps_status st;
+    if (mode == 1 && (st = check_relax(rp)) != MPS_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    if (capturing(hs)) return fail(MPS_E_NOT_CAPTURABLE, "mps_search during capture");
+    const DevModel &d = m->d;
+    const int32_t D = d.T + 1;
+    const int64_t nm = d.N * D;
+    if (nm >= ((int64_t)1 << 31)) return fail(MPS_E_INVALID_ARG, "too many moves");
+    if (repair_lds_bytes(d, k) > (size_t)m->max_lds)
+        return fail(MPS_E_INVALID_ARG, "repair state does not fit in LDS");
+    DeviceGuard g(m->device);
+    SearchBufs B;
+    float *score = B.get<float>(nm);
+    uint8_t *flags = B.get<uint8_t>(nm);
+    char *tws = B.get<char>(topk_ws_bytes(nm, k));
+    int64_t *idx = B.get<int64_t>(k);
+    int32_t *cnt = B.get<int32_t>(4);
+    float *x = nullptr, *grad = nullptr, *gain = nullptr, *lscore = nullptr;
+    char *saved = nullptr, *rws = nullptr, *ltws = nullptr;
+    int32_t *rblk = nullptr;
+    int8_t *rper = nullptr;
+    uint8_t *lflags = nullptr;
+    if (mode == 1) {
+        x = B.get<float>((size_t)d.N * d.T);
+        grad = B.get<float>((size_t)d.N * d.T);
+        saved = B.get<char>(relaxed_saved_bytes(d));
+        rws = B.get<char>(rank_ws_bytes(d, k));
+        rblk = B.get<int32_t>(k);
+        rper = B.get<int8_t>(k);
+        gain = B.get<float>(k);
+        lscore = B.get<float>(k);
+        lflags = B.get<uint8_t>(k);
+        ltws = B.get<char>(topk_ws_bytes(k, k));
+    }
+    for (void *p : B.ptrs)
+        if (!p) return fail(MPS_E_OUT_OF_MEMORY, "mps_search buffers");
+    mps_moves ex{1, 1, 0, nullptr, nullptr};
+    mps_moves lst{0, 1, k, rblk, rper};
+    int64_t iters = 0, evals = 0, applied_total = 0;
+    int32_t h_applied = 0;
+    auto round_exhaustive = [&]() -> hipError_t {
+        hipError_t e = launch_eval(d, ex, score, flags, nullptr, nullptr, nullptr, hs);
+        if (e == hipSuccess)
+            e = launch_topk(score, flags, nm, k, MPS_PREC_OK, MPS_NOOP | MPS_BAD, idx, nullptr,
+                            cnt, tws, hs);
+        if (e == hipSuccess) e = launch_repair(d, ex, idx, cnt, k, 0, cnt + 1, hs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&h_applied, cnt + 1, sizeof(int32_t), hipMemcpyDeviceToHost, hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+        evals += nm;
+        return e;
+    };
+    auto round_gradient = [&]() -> hipError_t {
+        hipError_t e = launch_integer_x(d, x, hs);
+        if (e == hipSuccess) e = launch_relaxed_fwd(d, x, *rp, nullptr, saved, m->relax_ws, hs);
+        if (e == hipSuccess) e = launch_relaxed_bwd(d, x, *rp, saved, nullptr, grad, hs);
+        if (e == hipSuccess) e = launch_rank(d, grad, k, rblk, rper, gain, cnt + 2, rws, hs);
+        if (e == hipSuccess) e = launch_eval(d, lst, lscore, lflags, nullptr, nullptr, nullptr, hs);
+        if (e == hipSuccess)
+            e = launch_topk(lscore, lflags, k, k, MPS_PREC_OK, MPS_NOOP | MPS_BAD, idx, nullptr,
+                            cnt, ltws, hs);
+        if (e == hipSuccess) e = launch_repair(d, lst, idx, cnt, k, 0, cnt + 1, hs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&h_applied, cnt + 1, sizeof(int32_t), hipMemcpyDeviceToHost, hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+        evals += k;
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    while (iters < max_iter) {
+        e = mode == 0 ? round_exhaustive() : round_gradient();
+        if (e != hipSuccess) break;
+        ++iters;
+        applied_total += h_applied;
+        if (h_applied == 0) {
+            if (mode == 0) break;
+            e = round_exhaustive();
+            if (e != hipSuccess) break;
+            ++iters;
+            applied_total += h_applied;
+            if (h_applied == 0) break;
+        }
+    }
+    if (e != hipSuccess) return dev_fail(e, "search");
+    mps_objective obj;
+    if ((st = mps_get_objective(m, &obj, stream)) != MPS_OK) return st;
+    if (out) {
+        out->iterations = iters;
+        out->evaluations = evals;
+        out->applied = applied_total;
+        out->J = obj.J;
+    }
+    return MPS_OK;
 }
 
 }  // extern "C"

@@ -92,6 +92,17 @@ hipError_t launch_repair(const DevModel &m, const mps_moves &mv,
                          int32_t max_cand, int32_t hard, int32_t *applied,
                          hipStream_t st);
 
+size_t relaxed_saved_bytes(const DevModel &m);
+size_t relaxed_ws_bytes(const DevModel &m);
+hipError_t launch_relaxed_fwd(const DevModel &m, const float *x, const mps_relax_params &rp,
+                              double *J_out, void *saved, void *ws, hipStream_t st);
+hipError_t launch_relaxed_bwd(const DevModel &m, const float *x, const mps_relax_params &rp,
+                              const void *saved, const double *dJ, float *grad, hipStream_t st);
+size_t rank_ws_bytes(const DevModel &m, int32_t k);
+hipError_t launch_rank(const DevModel &m, const float *grad, int32_t k, int32_t *blk,
+                       int8_t *per, float *gain_out, int32_t *count, void *ws, hipStream_t st);
+hipError_t launch_integer_x(const DevModel &m, float *x, hipStream_t st);
+
 // Precedence neighbours under the 1-5 stencil; shared by the kernels.
 __device__ __forceinline__ void grid_coords(const DevModel &m, int32_t b,
                                             int32_t &x, int32_t &y, int32_t &z) {

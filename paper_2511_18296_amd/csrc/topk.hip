@@ -77,7 +77,8 @@ __device__ __forceinline__ float unord_f32(uint32_t o) {
 __device__ __forceinline__ bool item_key(const float *score, const uint8_t *flags, int64_t i,
                                          uint8_t req, uint8_t forbid, uint64_t &key) {
     const uint8_t f = flags[i];
-    const float s = score[i];
+    // -0 + +0 = +0: both zeros compare equal, as in IEEE comparison
+    const float s = score[i] + 0.0f;
     if ((f & req) != req || (f & forbid) != 0 || isnan(s)) return false;
     key = ((uint64_t)ord_f32(s) << 32) | (uint64_t)(0xffffffffu - (uint32_t)i);
     return true;
