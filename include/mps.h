@@ -148,6 +148,17 @@ mps_status mps_get_objective(mps_model *m, mps_objective *out, void *stream);
  * (double[7]: mu, sigma, R, Pp, Pm, J, n_prec_viol); capturable. */
 mps_status mps_objective_async(mps_model *m, double *out, void *stream);
 
+/* Search state: the schedule and everything derived from it (per-scenario
+ * NPV, period tonnages, objective terms, penalty tables) occupy one device
+ * region of mps_state_bytes(m) bytes.  mps_state_save copies it into `buf`
+ * (device, caller-owned), mps_state_restore copies such a buffer back: a
+ * checkpoint of the search that is restored without re-reading the block
+ * values.  A buffer restores only into the model it was saved from (or one
+ * built from the same inputs).  Capturable (device-to-device copies). */
+size_t mps_state_bytes(const mps_model *m);
+mps_status mps_state_save(mps_model *m, void *buf, void *stream);
+mps_status mps_state_restore(mps_model *m, const void *buf, void *stream);
+
 /* Evaluate moves against the current schedule (Alg. 5, every destination):
  *   score  float [n_moves]  J(p') - J(p), FP32 arithmetic on FP64 state;
  *   flags  uint8 [n_moves]  MPS_* bits;

@@ -87,6 +87,9 @@ def _load():
         "mps_rank_ws_bytes": ([vp, i32], C.c_size_t),
         "mps_rank_moves": ([vp, vp, i32, vp, vp, vp, vp, vp, C.c_size_t, vp], st),
         "mps_search": ([vp, i32, i32, vp, i32, vp, vp], st),
+        "mps_state_bytes": ([vp], C.c_size_t),
+        "mps_state_save": ([vp, vp, vp], st),
+        "mps_state_restore": ([vp, vp, vp], st),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -103,7 +106,8 @@ EXPORTS = ("mps_last_error", "mps_version", "mps_device_count", "mps_build_model
            "mps_get_schedule", "mps_get_objective", "mps_objective_async",
            "mps_eval_moves", "mps_topk_ws_bytes", "mps_topk", "mps_repair",
            "mps_relaxed_saved_bytes", "mps_relaxed_fwd", "mps_relaxed_bwd",
-           "mps_rank_ws_bytes", "mps_rank_moves", "mps_search")
+           "mps_rank_ws_bytes", "mps_rank_moves", "mps_search", "mps_state_bytes",
+           "mps_state_save", "mps_state_restore")
 
 
 def check(status: int):
@@ -216,6 +220,17 @@ class Model:
             out = torch.empty(self.N, dtype=torch.int8, device=self.device)
         check(lib.mps_get_schedule(self.h, _ptr(out), _stream(stream)))
         return out
+
+    def save_state(self, buf=None, stream=None):
+        """Checkpoint of the search state (device uint8 tensor)."""
+        n = int(lib.mps_state_bytes(self.h))
+        if buf is None:
+            buf = torch.empty(n, dtype=torch.uint8, device=self.device)
+        check(lib.mps_state_save(self.h, _ptr(buf), _stream(stream)))
+        return buf
+
+    def restore_state(self, buf, stream=None):
+        check(lib.mps_state_restore(self.h, _ptr(buf), _stream(stream)))
 
     def objective(self, stream=None) -> dict:
         o = Objective()

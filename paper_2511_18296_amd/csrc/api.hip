@@ -89,9 +89,12 @@ struct mps_model {
     size_t bytes = 0;
     size_t limit = 0;      // test-only allocation cap (0 = none)
     double *partial = nullptr;
-    int chunks = 8;
+    int chunks = 16;
     double *obj_dev = nullptr;   // double[7]
     void *relax_ws = nullptr;    // partial sums of the relaxed forward pass
+    void *gather = nullptr;      // candidate records of a repair walk
+    char *arena = nullptr;       // mutable search state (see mps_state_save)
+    size_t arena_bytes = 0;
     int max_lds = 65536;
 
     template <class T>
@@ -222,11 +225,13 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     d.ton_min = tmin;
     d.ton_max = tmax;
 
-    float *v_, *ton32, *mb32, *Vb32, *e32, *part_rem_a, *blk_c, *blk_rem;
+    float *v_, *ton32, *mb32, *Vb32, *e32, *blk_c, *blk_rem;
     uint32_t *ore_, *full_add, *full_rem;
-    double *ton64, *mb64, *Vb64, *Ns, *O, *M, *d64, *part_add_O;
+    double *ton64, *mb64, *Vb64, *Ns, *O, *M, *d64;
     int8_t *p;
-    int32_t *n_pa, *n_pr, *pa_s, *pr_s, *blk_info;
+    int32_t *tcnt, *trng, *blk_info;
+    AddEntry *ladd, *padd;
+    RemEntry *lrem, *prem;
     DevScalars *sc;
 #define ALLOC(ptr, cnt)                      \
     if ((st = m->alloc(ptr, cnt)) != MPS_OK) { \
@@ -242,21 +247,44 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     ALLOC(Vb64, N);
     ALLOC(mb32, N);
     ALLOC(Vb32, N);
-    ALLOC(p, N);
-    ALLOC(Ns, S);
-    ALLOC(O, (size_t)T * S);
-    ALLOC(M, T);
-    ALLOC(e32, S);
-    ALLOC(sc, 1);
     ALLOC(d64, T + 1);
-    ALLOC(full_add, (size_t)T * W);
-    ALLOC(full_rem, (size_t)T * W);
-    ALLOC(n_pa, T);
-    ALLOC(n_pr, T);
-    ALLOC(pa_s, (size_t)T * S);
-    ALLOC(part_add_O, (size_t)T * S);
-    ALLOC(pr_s, (size_t)T * S);
-    ALLOC(part_rem_a, (size_t)T * S);
+    // Mutable search state (schedule, per-scenario NPV, period tonnages,
+    // scalars, penalty tables) in one arena, so that saving or restoring it
+    // is one device copy.
+    {
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t o = off;
+            off = (off + bytes + 255) & ~(size_t)255;
+            return o;
+        };
+        const size_t o_p = take((size_t)N), o_Ns = take(8 * (size_t)S),
+                     o_O = take(8 * (size_t)T * S), o_M = take(8 * (size_t)T),
+                     o_e = take(4 * (size_t)S), o_sc = take(sizeof(DevScalars)),
+                     o_fa = take(4 * (size_t)T * W), o_fr = take(4 * (size_t)T * W),
+                     o_cnt = take(8 * (size_t)T), o_la = take(sizeof(AddEntry) * (size_t)T * S),
+                     o_lr = take(sizeof(RemEntry) * (size_t)T * S), o_rg = take(16 * (size_t)T),
+                     o_pa = take(sizeof(AddEntry) * (size_t)T * S),
+                     o_pr = take(sizeof(RemEntry) * (size_t)T * S);
+        char *arena = nullptr;
+        ALLOC(arena, off);
+        m->arena = arena;
+        m->arena_bytes = off;
+        p = (int8_t *)(arena + o_p);
+        Ns = (double *)(arena + o_Ns);
+        O = (double *)(arena + o_O);
+        M = (double *)(arena + o_M);
+        e32 = (float *)(arena + o_e);
+        sc = (DevScalars *)(arena + o_sc);
+        full_add = (uint32_t *)(arena + o_fa);
+        full_rem = (uint32_t *)(arena + o_fr);
+        tcnt = (int32_t *)(arena + o_cnt);
+        ladd = (AddEntry *)(arena + o_la);
+        lrem = (RemEntry *)(arena + o_lr);
+        trng = (int32_t *)(arena + o_rg);
+        padd = (AddEntry *)(arena + o_pa);
+        prem = (RemEntry *)(arena + o_pr);
+    }
     ALLOC(blk_c, N);
     ALLOC(blk_rem, N);
     ALLOC(blk_info, N);
@@ -266,6 +294,9 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
         char *rw = nullptr;
         ALLOC(rw, relaxed_ws_bytes(d));
         m->relax_ws = rw;
+        char *gw = nullptr;
+        ALLOC(gw, repair_gather_bytes(S, W));
+        m->gather = gw;
     }
 #undef ALLOC
     d.v = v_;
@@ -285,12 +316,12 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     d.d64 = d64;
     d.tab.full_add = full_add;
     d.tab.full_rem = full_rem;
-    d.tab.n_part_add = n_pa;
-    d.tab.n_part_rem = n_pr;
-    d.tab.part_add_s = pa_s;
-    d.tab.part_add_O = part_add_O;
-    d.tab.part_rem_s = pr_s;
-    d.tab.part_rem_a = part_rem_a;
+    d.tab.cnt = tcnt;
+    d.tab.add = ladd;
+    d.tab.rem = lrem;
+    d.tab.rng = trng;
+    d.tab.add_packed = padd;
+    d.tab.rem_packed = prem;
     d.blk_c = blk_c;
     d.blk_rem = blk_rem;
     d.blk_info = blk_info;
@@ -477,8 +508,28 @@ mps_status mps_repair(mps_model *m, const mps_moves *moves, const int64_t *idx,
                     m->max_lds);
     DeviceGuard g(m->device);
     hipError_t e = launch_repair(m->d, *moves, idx, count, max_cand, hard_capacity, applied,
-                                 (hipStream_t)stream);
+                                 m->gather, (hipStream_t)stream);
     return e == hipSuccess ? MPS_OK : dev_fail(e, "repair");
+}
+
+size_t mps_state_bytes(const mps_model *m) { return m ? m->arena_bytes : 0; }
+
+mps_status mps_state_save(mps_model *m, void *buf, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    if (!buf) return fail(MPS_E_INVALID_ARG, "buf is NULL");
+    DeviceGuard g(m->device);
+    hipError_t e = hipMemcpyAsync(buf, m->arena, m->arena_bytes, hipMemcpyDeviceToDevice,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "state save");
+}
+
+mps_status mps_state_restore(mps_model *m, const void *buf, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    if (!buf) return fail(MPS_E_INVALID_ARG, "buf is NULL");
+    DeviceGuard g(m->device);
+    hipError_t e = hipMemcpyAsync(m->arena, buf, m->arena_bytes, hipMemcpyDeviceToDevice,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "state restore");
 }
 
 size_t mps_relaxed_saved_bytes(const mps_model *m) {
@@ -591,7 +642,7 @@ mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_par
         if (e == hipSuccess)
             e = launch_topk(score, flags, nm, k, MPS_PREC_OK, MPS_NOOP | MPS_BAD, idx, nullptr,
                             cnt, tws, hs);
-        if (e == hipSuccess) e = launch_repair(d, ex, idx, cnt, k, 0, cnt + 1, hs);
+        if (e == hipSuccess) e = launch_repair(d, ex, idx, cnt, k, 0, cnt + 1, m->gather, hs);
         if (e == hipSuccess)
             e = hipMemcpyAsync(&h_applied, cnt + 1, sizeof(int32_t), hipMemcpyDeviceToHost, hs);
         if (e == hipSuccess) e = hipStreamSynchronize(hs);
@@ -607,7 +658,7 @@ mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_par
         if (e == hipSuccess)
             e = launch_topk(lscore, lflags, k, k, MPS_PREC_OK, MPS_NOOP | MPS_BAD, idx, nullptr,
                             cnt, ltws, hs);
-        if (e == hipSuccess) e = launch_repair(d, lst, idx, cnt, k, 0, cnt + 1, hs);
+        if (e == hipSuccess) e = launch_repair(d, lst, idx, cnt, k, 0, cnt + 1, m->gather, hs);
         if (e == hipSuccess)
             e = hipMemcpyAsync(&h_applied, cnt + 1, sizeof(int32_t), hipMemcpyDeviceToHost, hs);
         if (e == hipSuccess) e = hipStreamSynchronize(hs);

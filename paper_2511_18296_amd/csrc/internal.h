@@ -23,25 +23,39 @@ struct DevScalars {
 };
 
 // Per-period tables of the processing-capacity penalty.  For period t and
-// scenario s with O = O[t][s] (FP64) and a = O - proc_cap:
+// scenario s with O = O[t][s] (FP64):
 //   add term (block b moved INTO t):  hinge(O + ton_b) - hinge(O)
-//     full    : O >= cap and O + ton_min > cap  -> value ton_b, always a
-//               capacity violation
-//     partial : otherwise, if O + ton_max > cap -> evaluated per block in
-//               FP64 (value and violation)
-//     none    : O + ton_max <= cap              -> 0, never a violation
+//     full add    : O >= cap and O + ton_min > cap -> value ton_b and a
+//                   capacity violation for every block (bit in full_add)
+//     partial add : otherwise, if O + ton_max > cap -> list entry with
+//                   d = cap - O (value max(0, ton_b - d)) and the exact FP64
+//                   threshold tau = min{x >= 0 : O + x > cap} (violation iff
+//                   ton_b >= tau, the same decision as evaluating O + ton_b > cap)
+//     neither     : O + ton_max <= cap               -> 0, never a violation
 //   removal term (block b moved OUT of t): hinge(O - ton_b) - hinge(O)
-//     = -clamp(a, 0, ton_b): full (-ton_b) when a >= ton_max, zero when
-//     a <= 0, partial (-min(a, ton_b)) otherwise.
+//     = -clamp(O - cap, 0, ton_b)
+//     full rem    : O - cap >= ton_max               -> -ton_b (bit in full_rem)
+//     partial rem : 0 < O - cap < ton_max            -> list entry a = O - cap,
+//                   value -min(a, ton_b)
+// Lists are per period, scenario-ascending, entry j of period t at [t*S + j].
+struct AddEntry {
+    double tau;
+    float d;
+    int32_t s;
+};
+struct RemEntry {
+    float a;
+    int32_t s;
+};
 struct PeriodTables {
-    uint32_t *full_add;    // [T][W] bit s%32 of word s/32
-    uint32_t *full_rem;    // [T][W]
-    int32_t *n_part_add;   // [T]
-    int32_t *n_part_rem;   // [T]
-    int32_t *part_add_s;   // [T][S] scenario ids, ascending
-    double *part_add_O;    // [T][S] O[t][s] of those scenarios
-    int32_t *part_rem_s;   // [T][S]
-    float *part_rem_a;     // [T][S] O[t][s] - cap of those scenarios
+    uint32_t *full_add;   // [T][W] bit s%32 of word s/32
+    uint32_t *full_rem;   // [T][W]
+    int32_t *cnt;         // [2][T] list lengths per period (add, rem)
+    AddEntry *add;        // [T][S] per-period slots (written by the table kernel)
+    RemEntry *rem;        // [T][S]
+    int32_t *rng;         // [4][T]: packed add begin/end, rem begin/end
+    AddEntry *add_packed; // [T*S] concatenated lists
+    RemEntry *rem_packed; // [T*S]
 };
 
 struct DevModel {
@@ -87,10 +101,11 @@ hipError_t launch_topk(const float *score, const uint8_t *flags, int64_t n,
                        float *top_score, int32_t *count, void *ws,
                        hipStream_t st);
 size_t repair_lds_bytes(const DevModel &m, int32_t max_cand);
+size_t repair_gather_bytes(int32_t S, int32_t W);
 hipError_t launch_repair(const DevModel &m, const mps_moves &mv,
                          const int64_t *idx, const int32_t *count,
                          int32_t max_cand, int32_t hard, int32_t *applied,
-                         hipStream_t st);
+                         void *gather, hipStream_t st);
 
 size_t relaxed_saved_bytes(const DevModel &m);
 size_t relaxed_ws_bytes(const DevModel &m);

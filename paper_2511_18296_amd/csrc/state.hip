@@ -49,52 +49,71 @@ __global__ void k_copy_schedule(DevModel m, const int8_t *p_in) {
 // Partial sums over one chunk of blocks.  Row r < S: N_s and O[.][s] for
 // scenario s = r; row r == S: M[.], precedence violations and clamped
 // entries.  64 threads; each keeps private per-period accumulators in LDS.
+// Loads of eight blocks are issued before their accumulations so that the
+// loop is not bound by memory latency.
 // partial layout: [chunk][S+1][T+1]  (entry T of a scenario row holds N_s,
 // entry T of the last row the violation count).
+constexpr int kStU = 8;
+
 __global__ void __launch_bounds__(64) k_state_partial(DevModel m, const int8_t *p_in,
                                                       double *partial, int chunks) {
-    extern __shared__ double acc[];   // [T][64]
+    extern __shared__ double acc[];   // [T][64], then d[T+1]
     const int tid = threadIdx.x;
     const int ch = blockIdx.x;
     const int r = blockIdx.y;
     const int32_t T = m.T;
+    double *dl = acc + (size_t)T * 64;
     for (int t = 0; t < T; ++t) acc[t * 64 + tid] = 0.0;
-    int64_t per = (m.N + chunks - 1) / chunks;
-    int64_t b0 = (int64_t)ch * per, b1 = min(m.N, b0 + per);
+    for (int t = tid; t <= T; t += 64) dl[t] = m.d64[t];
+    __syncthreads();
+    const int64_t per = (m.N + chunks - 1) / chunks;
+    const int64_t b0 = (int64_t)ch * per, b1 = min(m.N, b0 + per);
     double nacc = 0.0;
     if (r < m.S) {
         const int32_t s = r;
         const float *vrow = m.v + (int64_t)s * m.N;
         const uint32_t *orow = m.ore + (int64_t)(s >> 5) * m.N;
         const uint32_t bit = 1u << (s & 31);
-        for (int64_t b = b0 + tid; b < b1; b += 64) {
-            int32_t t = p_in[b];
-            if (t < 0 || t > T) t = T;
-            nacc += (double)vrow[b] * m.d64[t];
-            if (t < T && (orow[b] & bit)) acc[t * 64 + tid] += m.ton64[b];
+        for (int64_t bb = b0 + tid; bb < b1; bb += 64 * kStU) {
+            int32_t tv[kStU];
+            float vv[kStU];
+            uint32_t ov[kStU];
+            double tn[kStU];
+#pragma unroll
+            for (int u = 0; u < kStU; ++u) {
+                const int64_t b = min(bb + 64 * u, b1 - 1);
+                tv[u] = m.p[b];
+                vv[u] = vrow[b];
+                ov[u] = orow[b];
+                tn[u] = m.ton64[b];
+            }
+#pragma unroll
+            for (int u = 0; u < kStU; ++u) {
+                if (bb + 64 * u >= b1) break;
+                const int32_t t = tv[u];
+                nacc += (double)vv[u] * dl[t];
+                if (t < T && (ov[u] & bit)) acc[t * 64 + tid] += tn[u];
+            }
         }
     } else {
+        const int32_t nxy = m.nx * m.ny;
         for (int64_t b = b0 + tid; b < b1; b += 64) {
-            int32_t t = p_in[b];
-            bool bad = (t < 0 || t > T);
-            if (bad) t = T;
+            const int32_t t0 = p_in[b];
+            const bool bad = (t0 < 0 || t0 > T);
+            const int32_t t = m.p[b];
             if (t < T) acc[t * 64 + tid] += m.ton64[b];
             // predecessor pairs with p[a] > p[b]
             int32_t x, y, z;
             grid_coords(m, (int32_t)b, x, y, z);
+            const int64_t a = b - nxy;
+            const int64_t ia[5] = {a, a - 1, a + 1, a - m.nx, a + m.nx};
+            const bool va[5] = {z > 0, z > 0 && x > 0, z > 0 && x + 1 < m.nx, z > 0 && y > 0,
+                                z > 0 && y + 1 < m.ny};
             double nv = bad ? 1.0 : 0.0;
-            if (z > 0) {
-                const int32_t nxy = m.nx * m.ny;
-                int64_t a = b - nxy;
-                auto pa = [&](int64_t i) {
-                    int32_t u = p_in[i];
-                    return (u < 0 || u > T) ? T : u;
-                };
-                if (pa(a) > t) nv += 1.0;
-                if (x > 0 && pa(a - 1) > t) nv += 1.0;
-                if (x + 1 < m.nx && pa(a + 1) > t) nv += 1.0;
-                if (y > 0 && pa(a - m.nx) > t) nv += 1.0;
-                if (y + 1 < m.ny && pa(a + m.nx) > t) nv += 1.0;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const int32_t pa = m.p[va[k] ? ia[k] : b];
+                if (va[k] && pa > t) nv += 1.0;
             }
             nacc += nv;
         }
@@ -102,9 +121,9 @@ __global__ void __launch_bounds__(64) k_state_partial(DevModel m, const int8_t *
     __syncthreads();
     double *out = partial + ((int64_t)ch * (m.S + 1) + r) * (T + 1);
     for (int t = tid; t < T; t += 64) {
-        double s = 0.0;
-        for (int j = 0; j < 64; ++j) s += acc[t * 64 + j];
-        out[t] = s;
+        double sum = 0.0;
+        for (int j = 0; j < 64; ++j) sum += acc[t * 64 + j];
+        out[t] = sum;
     }
     // fixed-order tree over the 64 lanes for the scalar accumulator
     __syncthreads();
@@ -140,7 +159,7 @@ hipError_t launch_set_schedule(const DevModel &m, const int8_t *p_in,
                                double *partial, int chunks, hipStream_t st) {
     int64_t g = (m.N + 255) / 256;
     hipLaunchKernelGGL(k_copy_schedule, dim3((unsigned)g), dim3(256), 0, st, m, p_in);
-    size_t lds = (size_t)m.T * 64 * sizeof(double);
+    size_t lds = ((size_t)m.T * 64 + m.T + 1) * sizeof(double);
     if (lds < 64 * sizeof(double)) lds = 64 * sizeof(double);
     hipLaunchKernelGGL(k_state_partial, dim3(chunks, m.S + 1), dim3(64), lds, st, m,
                        p_in, partial, chunks);
@@ -164,6 +183,21 @@ __device__ double block_sum_f64(double x, double *red) {
     double r = red[0];
     __syncthreads();
     return r;
+}
+
+// Smallest non-negative double x with O + x > cap in FP64 arithmetic (the sum
+// is monotone in x, so a bisection over the bit patterns of non-negative
+// doubles finds it); hi is known to exceed the threshold.
+__device__ double min_exceeding(double O, double cap, double hi) {
+    if (O + 0.0 > cap) return 0.0;
+    if (!(O + hi > cap)) return hi;   // not a partial entry; never taken
+    uint64_t lo_b = 0, hi_b = (uint64_t)__double_as_longlong(hi);
+    while (hi_b - lo_b > 1) {          // at most 64 halvings
+        const uint64_t mid = lo_b + (hi_b - lo_b) / 2;
+        if (O + __longlong_as_double((long long)mid) > cap) hi_b = mid;
+        else lo_b = mid;
+    }
+    return __longlong_as_double((long long)hi_b);
 }
 
 // Block T: mu, var, sigma, e_s and the objective terms.  Blocks t < T: the
@@ -209,18 +243,18 @@ __global__ void __launch_bounds__(256) k_prep(DevModel m) {
     const int lane = tid & 63, wave = tid >> 6;
     int32_t base_add = 0, base_rem = 0;
     for (int32_t s0 = 0; s0 < S; s0 += 256) {
-        int32_t s = s0 + tid;
-        bool in = s < S;
-        double O = in ? m.O[(int64_t)t * S + s] : 0.0;
-        bool full_add = in && O >= m.pcap && O + m.ton_min > m.pcap;
-        bool part_add = in && !full_add && O + m.ton_max > m.pcap;
-        double a = O - m.pcap;
-        bool full_rem = in && a >= m.ton_max;
-        bool part_rem = in && !full_rem && a > 0.0;
-        uint64_t bfa = __ballot(full_add), bfr = __ballot(full_rem);
-        uint64_t bpa = __ballot(part_add), bpr = __ballot(part_rem);
+        const int32_t s = s0 + tid;
+        const bool in = s < S;
+        const double O = in ? m.O[(int64_t)t * S + s] : 0.0;
+        const bool full_add = in && O >= m.pcap && O + m.ton_min > m.pcap;
+        const bool part_add = in && !full_add && O + m.ton_max > m.pcap;
+        const double a = O - m.pcap;
+        const bool full_rem = in && a >= m.ton_max;
+        const bool part_rem = in && !full_rem && a > 0.0;
+        const uint64_t bfa = __ballot(full_add), bfr = __ballot(full_rem);
+        const uint64_t bpa = __ballot(part_add), bpr = __ballot(part_rem);
         if (lane == 0) {
-            int32_t w0 = (s0 >> 5) + wave * 2;   // 64 scenarios = 2 words
+            const int32_t w0 = (s0 >> 5) + wave * 2;   // 64 scenarios = 2 words
             if (w0 < W) {
                 m.tab.full_add[(int64_t)t * W + w0] = (uint32_t)bfa;
                 m.tab.full_rem[(int64_t)t * W + w0] = (uint32_t)bfr;
@@ -236,33 +270,74 @@ __global__ void __launch_bounds__(256) k_prep(DevModel m) {
         __syncthreads();
         int32_t oa = base_add, orr = base_rem, ta = 0, tr = 0;
         for (int w = 0; w < 4; ++w) {
-            int32_t ca = woff[w] & 0xffff, cr = woff[w] >> 16;
-            if (w < wave) { oa += ca; orr += cr; }
+            const int32_t ca = woff[w] & 0xffff, cr = woff[w] >> 16;
+            if (w < wave) {
+                oa += ca;
+                orr += cr;
+            }
             ta += ca;
             tr += cr;
         }
-        uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         if (part_add) {
-            int32_t j = oa + (int32_t)__popcll(bpa & below);
-            m.tab.part_add_s[(int64_t)t * S + j] = s;
-            m.tab.part_add_O[(int64_t)t * S + j] = O;
+            const int32_t j = oa + (int32_t)__popcll(bpa & below);
+            AddEntry e;
+            e.tau = min_exceeding(O, m.pcap, 2.0 * m.ton_max);
+            e.d = (float)(m.pcap - O);
+            e.s = s;
+            m.tab.add[(int64_t)t * S + j] = e;
         }
         if (part_rem) {
-            int32_t j = orr + (int32_t)__popcll(bpr & below);
-            m.tab.part_rem_s[(int64_t)t * S + j] = s;
-            m.tab.part_rem_a[(int64_t)t * S + j] = (float)a;
+            const int32_t j = orr + (int32_t)__popcll(bpr & below);
+            RemEntry e;
+            e.a = (float)a;
+            e.s = s;
+            m.tab.rem[(int64_t)t * S + j] = e;
         }
         base_add += ta;
         base_rem += tr;
+        __syncthreads();
     }
     if (tid == 0) {
-        m.tab.n_part_add[t] = base_add;
-        m.tab.n_part_rem[t] = base_rem;
+        m.tab.cnt[t] = base_add;
+        m.tab.cnt[T + t] = base_rem;
+    }
+}
+
+// Concatenate the per-period partial lists (CSR): rng[0..T) add begin,
+// rng[T..2T) add end, rng[2T..3T) rem begin, rng[3T..4T) rem end.  One
+// workgroup of 256 threads.
+__global__ void __launch_bounds__(256) k_pack_tables(DevModel m) {
+    __shared__ int32_t off[2][MPS_MAX_PERIODS + 1];
+    const int tid = threadIdx.x;
+    const int32_t T = m.T, S = m.S;
+    if (tid < 2) {
+        int32_t run = 0;
+        for (int32_t t = 0; t < T; ++t) {
+            off[tid][t] = run;
+            run += m.tab.cnt[tid * T + t];
+        }
+        off[tid][T] = run;
+    }
+    __syncthreads();
+    for (int32_t t = tid; t < T; t += 256) {
+        m.tab.rng[t] = off[0][t];
+        m.tab.rng[T + t] = off[0][t + 1];
+        m.tab.rng[2 * T + t] = off[1][t];
+        m.tab.rng[3 * T + t] = off[1][t + 1];
+    }
+    for (int32_t t = 0; t < T; ++t) {
+        const int32_t ca = off[0][t + 1] - off[0][t], cr = off[1][t + 1] - off[1][t];
+        for (int32_t j = tid; j < ca; j += 256)
+            m.tab.add_packed[off[0][t] + j] = m.tab.add[(int64_t)t * S + j];
+        for (int32_t j = tid; j < cr; j += 256)
+            m.tab.rem_packed[off[1][t] + j] = m.tab.rem[(int64_t)t * S + j];
     }
 }
 
 hipError_t launch_prep(const DevModel &m, hipStream_t st) {
     hipLaunchKernelGGL(k_prep, dim3(m.T + 1), dim3(256), 0, st, m);
+    hipLaunchKernelGGL(k_pack_tables, dim3(1), dim3(256), 0, st, m);
     return hipGetLastError();
 }
 

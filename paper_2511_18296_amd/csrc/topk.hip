@@ -4,12 +4,20 @@
 //
 // Each qualifying item i gets the 64-bit key
 //   key = ord(score) << 32 | (0xffffffff - i)
-// where ord maps floats to unsigned integers monotonically.  Keys are unique
-// and "larger key" = "better item" (higher score, then smaller index), so the
-// top k items are the k largest keys.  A most-significant-digit radix select
-// (digits of 11/11/10 bits per 32-bit half) finds them with integer
-// histograms; survivors of each level are compacted; the final k keys are
-// sorted in LDS with a bitonic network.
+// where ord maps floats to unsigned integers monotonically (-0 and +0 equal).
+// Keys are unique and "larger key" = "better item" (higher score, then smaller
+// index), so the top k items are the k largest keys.  A most-significant-
+// digit radix select finds them:
+//   1. histogram of the top 11 bits over all items (every workgroup adds its
+//      LDS histogram; the last workgroup to finish picks the boundary digit);
+//   2. one pass moves items above the boundary digit to the output and items
+//      on it to a candidate buffer (wave-aggregated appends);
+//   3. one workgroup refines the candidates digit by digit (11/10/11/11/10
+//      more bits) until chosen keys and candidates fit in LDS together, then
+//      sorts that union with a bitonic network whose strides below 64 need
+//      no workgroup barrier.
+// Four launches in all; every count is an integer, so the result does not
+// depend on thread timing.
 #include <float.h>
 #include <math.h>
 
@@ -19,22 +27,26 @@ namespace mps {
 
 constexpr int kBins = 2048;
 constexpr int kLevels = 6;
+constexpr int kRefineThreads = 1024;
 __constant__ int c_shift[kLevels] = {53, 42, 32, 21, 10, 0};
 __constant__ int c_bits[kLevels] = {11, 11, 10, 11, 11, 10};
 
+constexpr int kRep = 8;   // replicas of the level-0 histogram and counters
+
 struct TopkCtrl {
-    uint64_t pad0;
     int32_t k_rem;      // how many keys are still to be chosen
     int32_t n_out;      // keys chosen so far (in out[])
-    int32_t n_cand[2];  // survivors per ping-pong buffer
-    int32_t sel;        // selected digit of the current level
-    int32_t take_all;   // every survivor of the level qualifies
-    int32_t pad1[2];
+    int32_t n_cand;     // candidates on the boundary digit after level 0
+    int32_t sel;        // boundary digit of level 0
+    int32_t take_all;   // every qualifying item is in the top k
+    uint32_t done;      // workgroups finished with the level-0 histogram
+    int32_t out_next[kRep];    // next free slot of each replica's output region
+    int32_t cand_next[kRep];   // next free slot of each replica's candidate region
 };
 
 struct TopkWs {
     TopkCtrl *ctrl;
-    uint32_t *hist;   // [kBins]
+    uint32_t *hist;   // [kRep][kBins]
     uint64_t *out;    // [k]
     uint64_t *cand0;  // [n]
     uint64_t *cand1;  // [n]
@@ -43,19 +55,19 @@ struct TopkWs {
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t topk_ws_bytes(int64_t n, int32_t k) {
-    size_t nn = n > 0 ? (size_t)n : 1;
-    return a256(sizeof(TopkCtrl)) + a256(sizeof(uint32_t) * kBins) +
+    const size_t nn = n > 0 ? (size_t)n : 1;
+    return a256(sizeof(TopkCtrl)) + a256(sizeof(uint32_t) * kBins * kRep) +
            a256(sizeof(uint64_t) * (size_t)k) + 2 * a256(sizeof(uint64_t) * nn);
 }
 
 static TopkWs carve_ws(void *ws, int64_t n, int32_t k) {
     char *p = (char *)ws;
-    size_t nn = n > 0 ? (size_t)n : 1;
+    const size_t nn = n > 0 ? (size_t)n : 1;
     TopkWs w;
     w.ctrl = (TopkCtrl *)p;
     p += a256(sizeof(TopkCtrl));
     w.hist = (uint32_t *)p;
-    p += a256(sizeof(uint32_t) * kBins);
+    p += a256(sizeof(uint32_t) * kBins * kRep);
     w.out = (uint64_t *)p;
     p += a256(sizeof(uint64_t) * (size_t)k);
     w.cand0 = (uint64_t *)p;
@@ -65,12 +77,12 @@ static TopkWs carve_ws(void *ws, int64_t n, int32_t k) {
 }
 
 __device__ __forceinline__ uint32_t ord_f32(float f) {
-    uint32_t u = __float_as_uint(f);
+    const uint32_t u = __float_as_uint(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
 __device__ __forceinline__ float unord_f32(uint32_t o) {
-    uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    const uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
     return __uint_as_float(u);
 }
 
@@ -84,199 +96,325 @@ __device__ __forceinline__ bool item_key(const float *score, const uint8_t *flag
     return true;
 }
 
-__global__ void k_topk_init(TopkWs w, int32_t k) {
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x) w.hist[i] = 0;
-    if (threadIdx.x == 0) {
-        w.ctrl->k_rem = k;
-        w.ctrl->n_out = 0;
-        w.ctrl->n_cand[0] = 0;
-        w.ctrl->n_cand[1] = 0;
-        w.ctrl->sel = 0;
-        w.ctrl->take_all = 0;
-    }
-}
-
 __device__ __forceinline__ int digit_of(uint64_t key, int level) {
     return (int)((key >> c_shift[level]) & ((1ull << c_bits[level]) - 1ull));
 }
 
-__device__ void flush_hist(uint32_t *lh, uint32_t *gh) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x) {
-        uint32_t c = lh[i];
-        if (c) atomicAdd(gh + i, c);
+// Append `key` where pred holds: one atomic per wave, positions by prefix
+// popcount (the order inside the buffer is irrelevant: keys are sorted last).
+// Every lane of the wave must call it.
+__device__ __forceinline__ void wave_append(bool pred, uint64_t key, uint64_t *buf,
+                                            int32_t *cnt) {
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(cnt, (int32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) {
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        buf[base + (int32_t)__popcll(mask & below)] = key;
     }
 }
 
-// Level 0 histogram straight from the scores.
-__global__ void __launch_bounds__(256) k_hist_src(const float *score, const uint8_t *flags,
+__global__ void k_topk_init(TopkWs w, int32_t k) {
+    for (int i = threadIdx.x; i < kBins * kRep; i += blockDim.x) w.hist[i] = 0;
+    if (threadIdx.x == 0) {
+        w.ctrl->k_rem = k;
+        w.ctrl->n_out = 0;
+        w.ctrl->n_cand = 0;
+        w.ctrl->sel = 0;
+        w.ctrl->take_all = 0;
+        w.ctrl->done = 0;
+    }
+}
+
+// The digit at which the running count from the top bin reaches k_rem, in an
+// LDS histogram h of nb bins (nb a multiple of 256).  res = {digit or -1,
+// count strictly above it, total}.  Called by every thread of the block
+// (blockDim a multiple of 64, at least 256): threads 0..255 own slices of
+// nb/256 bins counted from the top, a wave-level inclusive scan plus the
+// four wave totals give each slice its running count, and the one slice
+// whose range contains k_rem walks its bins.
+__device__ void select_digit(const uint32_t *h, int nb, int32_t k_rem, uint32_t *part,
+                             int32_t *res) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int per = nb >> 8;
+    uint32_t c = 0;
+    if (tid < 256)
+        for (int j = 0; j < per; ++j) c += h[nb - 1 - (tid * per + j)];
+    uint32_t x = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (tid < 256 && lane == 63) part[tid >> 6] = x;
+    if (tid == 0) {
+        res[0] = -1;
+        res[1] = 0;
+    }
+    __syncthreads();
+    if (tid < 256) {
+        uint32_t off = 0;
+        for (int w = 0; w < (tid >> 6); ++w) off += part[w];
+        const uint32_t incl = x + off, excl = incl - c;
+        if (excl < (uint32_t)k_rem && (uint32_t)k_rem <= incl) {
+            uint32_t r = excl;
+            for (int j = 0; j < per; ++j) {
+                const int bin = nb - 1 - (tid * per + j);
+                if (r + h[bin] >= (uint32_t)k_rem) {
+                    res[0] = bin;
+                    res[1] = (int32_t)r;
+                    break;
+                }
+                r += h[bin];
+            }
+        }
+        if (tid == 255) res[2] = (int32_t)incl;
+    }
+    __syncthreads();
+}
+
+// Items per thread of the two full passes; a workgroup covers a contiguous
+// range of 256 * kItems items and issues all their loads before using them.
+constexpr int kItems = 8;
+
+// Level-0 histogram over all items.  Workgroup g adds its LDS histogram to
+// replica g % kRep; the last workgroup sums the replicas, selects the digit,
+// and lays out the output and candidate regions of each replica back to back
+// (replica r's counts are exactly the items workgroups g = r (mod kRep) will
+// append in the next pass, which covers the same items per workgroup).
+__global__ void __launch_bounds__(256) k_hist0(const float *score, const uint8_t *flags,
+                                               int64_t n, uint8_t req, uint8_t forbid,
+                                               TopkWs w) {
+    __shared__ uint32_t lh[kBins];
+    __shared__ uint32_t part[256];
+    __shared__ int32_t res[3];
+    __shared__ int last;
+    for (int i = threadIdx.x; i < kBins; i += 256) lh[i] = 0;
+    const int64_t base = (int64_t)blockIdx.x * 256 * kItems + threadIdx.x;
+    uint64_t key[kItems];
+    bool q[kItems];
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        const int64_t i = base + 256 * u;
+        q[u] = i < n && item_key(score, flags, i, req, forbid, key[u]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kItems; ++u)
+        if (q[u]) atomicAdd(&lh[digit_of(key[u], 0)], 1u);
+    __syncthreads();
+    uint32_t *rep = w.hist + (size_t)(blockIdx.x % kRep) * kBins;
+    for (int i = threadIdx.x; i < kBins; i += 256) {
+        const uint32_t c = lh[i];
+        if (c) atomicAdd(rep + i, c);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&w.ctrl->done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int i = threadIdx.x; i < kBins; i += 256) {
+        uint32_t c = 0;
+        for (int r = 0; r < kRep; ++r)
+            c += __hip_atomic_load(w.hist + (size_t)r * kBins + i, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        lh[i] = c;
+    }
+    __syncthreads();
+    const int32_t k_rem = w.ctrl->k_rem;
+    select_digit(lh, kBins, k_rem, part, res);
+    const bool take_all = res[0] < 0 || res[2] <= k_rem;
+    const int sel = take_all ? -1 : res[0];
+    // per-replica region sizes: items above sel (all items with take_all)
+    // and items on sel
+    if (threadIdx.x < kRep) {
+        const int r = threadIdx.x;
+        int32_t above = 0, equal = 0;
+        for (int b = sel + 1; b < kBins; ++b)
+            above += (int32_t)__hip_atomic_load(w.hist + (size_t)r * kBins + b, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        if (sel >= 0)
+            equal = (int32_t)__hip_atomic_load(w.hist + (size_t)r * kBins + sel,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        part[r] = (uint32_t)above;
+        part[kRep + r] = (uint32_t)equal;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t oa = 0, oc = 0;
+        for (int r = 0; r < kRep; ++r) {
+            w.ctrl->out_next[r] = oa;
+            w.ctrl->cand_next[r] = oc;
+            oa += (int32_t)part[r];
+            oc += (int32_t)part[kRep + r];
+        }
+        w.ctrl->n_out = oa;
+        w.ctrl->n_cand = oc;
+        w.ctrl->take_all = take_all ? 1 : 0;
+        w.ctrl->sel = sel;
+        if (!take_all) w.ctrl->k_rem = k_rem - res[1];
+    }
+}
+
+// Items above the boundary digit -> out; on it -> cand0 (all qualifying items
+// -> out with take_all).  Each workgroup counts its items in LDS, reserves its
+// ranges with one atomic per buffer on its replica's counters, then writes.
+__global__ void __launch_bounds__(256) k_compact0(const float *score, const uint8_t *flags,
                                                   int64_t n, uint8_t req, uint8_t forbid,
                                                   TopkWs w) {
-    __shared__ uint32_t lh[kBins];
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x) lh[i] = 0;
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t key;
-        if (item_key(score, flags, i, req, forbid, key)) atomicAdd(&lh[digit_of(key, 0)], 1u);
+    __shared__ int32_t cnt[2], base_s[2];
+    const int take_all = w.ctrl->take_all;
+    const int sel = w.ctrl->sel;
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    const int64_t base = (int64_t)blockIdx.x * 256 * kItems + threadIdx.x;
+    uint64_t key[kItems];
+    bool q[kItems];
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        const int64_t i = base + 256 * u;
+        q[u] = i < n && item_key(score, flags, i, req, forbid, key[u]);
     }
-    flush_hist(lh, w.hist);
-}
-
-// Histogram of level `level` over the survivors in cand (count at *cnt).
-__global__ void __launch_bounds__(256) k_hist_cand(const uint64_t *cand, const int32_t *cnt,
-                                                   int level, TopkWs w) {
-    __shared__ uint32_t lh[kBins];
-    const int64_t n = *cnt;
-    if (w.ctrl->take_all || n == 0 || (int64_t)blockIdx.x * blockDim.x >= n) return;
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x) lh[i] = 0;
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&lh[digit_of(cand[i], level)], 1u);
-    flush_hist(lh, w.hist);
+    // local positions
+    int32_t pos[kItems];
+    int8_t dst[kItems];
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        const int d = q[u] ? digit_of(key[u], 0) : -1;
+        const bool to_out = q[u] && (take_all || d > sel);
+        const bool to_cand = q[u] && !take_all && d == sel;
+        dst[u] = to_out ? 0 : (to_cand ? 1 : -1);
+        pos[u] = -1;
+        const int lane = threadIdx.x & 63;
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const uint64_t mask = __ballot(dst[u] == b);
+            if (mask == 0) continue;
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            int32_t wb = 0;
+            if (lane == leader) wb = atomicAdd(&cnt[b], (int32_t)__popcll(mask));
+            wb = __shfl(wb, leader);
+            if (dst[u] == b) pos[u] = wb + (int32_t)__popcll(mask & below);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const int r = blockIdx.x % kRep;
+        int32_t *next = threadIdx.x == 0 ? &w.ctrl->out_next[r] : &w.ctrl->cand_next[r];
+        base_s[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(next, cnt[threadIdx.x]) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        if (dst[u] == 0) w.out[base_s[0] + pos[u]] = key[u];
+        else if (dst[u] == 1) w.cand0[base_s[1] + pos[u]] = key[u];
+    }
 }
 
-// Pick the digit at which the running count from the top reaches k_rem.
-// 256 threads, 8 bins each.  Clears the histogram for the next level.
-__global__ void __launch_bounds__(256) k_select(TopkWs w, int level, int32_t n_survivors_known,
-                                                const int32_t *n_surv) {
+// One workgroup: while the chosen keys plus the candidates exceed kSortCap,
+// refine the candidates by the next digit; then sort chosen and candidate
+// keys together (keys are unique, so the first min(k, total) of the sorted
+// union are exactly the top k) and write the outputs.
+constexpr int kSortCap = 8192;
+
+__global__ void __launch_bounds__(kRefineThreads) k_refine_sort(TopkWs w, int32_t k,
+                                                                int64_t *idx, float *top_score,
+                                                                int32_t *count) {
+    extern __shared__ uint64_t keys[];   // [kSortCap]
+    __shared__ uint32_t lh[kBins];
     __shared__ uint32_t part[256];
-    __shared__ int32_t sel_s, above_s, total_s;
+    __shared__ int32_t res[3];
+    __shared__ int32_t n_src_s, n_dst_s, n_out_s, k_rem_s;
     const int tid = threadIdx.x;
-    TopkCtrl *c = w.ctrl;
-    if (c->take_all) return;
-    const int nb = 1 << c_bits[level];
-    const int per = nb / 256 > 0 ? nb / 256 : 1;
-    // thread tid owns bins [tid*per, tid*per+per) counted from the top
-    uint32_t loc = 0;
-    for (int j = 0; j < per; ++j) {
-        int bin = nb - 1 - (tid * per + j);
-        if (bin >= 0) loc += w.hist[bin];
-    }
-    part[tid] = loc;
-    __syncthreads();
+    const TopkCtrl *c = w.ctrl;
     if (tid == 0) {
-        const int32_t k_rem = c->k_rem;
-        uint32_t run = 0;
-        int32_t sel = -1, above = 0;
-        for (int t = 0; t < 256 && sel < 0; ++t) {
-            if (run + part[t] >= (uint32_t)k_rem) {
-                for (int j = 0; j < per; ++j) {
-                    int bin = nb - 1 - (t * per + j);
-                    if (bin < 0) break;
-                    uint32_t h = w.hist[bin];
-                    if (run + h >= (uint32_t)k_rem) {
-                        sel = bin;
-                        above = (int32_t)run;
-                        break;
-                    }
-                    run += h;
-                }
-            } else {
-                run += part[t];
-            }
-        }
-        uint32_t total = 0;
-        for (int t = 0; t < 256; ++t) total += part[t];
-        sel_s = sel;
-        above_s = above;
-        total_s = (int32_t)total;
+        n_src_s = c->take_all ? 0 : c->n_cand;
+        n_out_s = c->n_out;
+        k_rem_s = c->k_rem;
     }
     __syncthreads();
-    for (int i = tid; i < kBins; i += 256) w.hist[i] = 0;
-    if (tid == 0) {
-        if (sel_s < 0 || total_s <= c->k_rem) {
-            c->take_all = 1;   // every survivor is in the top k
-        } else {
-            c->sel = sel_s;
-            c->k_rem -= above_s;
+    uint64_t *src = w.cand0, *dst = w.cand1;
+    for (int level = 1; level < kLevels; ++level) {
+        const int32_t ns = n_src_s;
+        if (ns == 0 || n_out_s + ns <= kSortCap) break;
+        const int nb = 1 << c_bits[level];
+        for (int i = tid; i < nb; i += kRefineThreads) lh[i] = 0;
+        if (tid == 0) n_dst_s = 0;
+        __syncthreads();
+        for (int32_t i = tid; i < ns; i += kRefineThreads)
+            atomicAdd(&lh[digit_of(src[i], level)], 1u);
+        __syncthreads();
+        const int32_t k_rem = k_rem_s;
+        select_digit(lh, nb, k_rem, part, res);
+        const bool take_all = res[0] < 0 || res[2] <= k_rem;
+        const int sel = res[0];
+        const bool last = level == kLevels - 1;
+        // digit above -> out; equal -> dst (keys are unique, so at the last
+        // level the equal digit is taken as well)
+        const int32_t n_up = ((ns + 63) / 64) * 64;
+        for (int32_t i = tid; i < n_up; i += kRefineThreads) {
+            const bool in = i < ns;
+            const uint64_t key = in ? src[i] : 0ull;
+            const int d = in ? digit_of(key, level) : -1;
+            const bool to_out = in && (take_all || d > sel || (last && d == sel));
+            const bool to_dst = in && !take_all && !last && d == sel;
+            wave_append(to_out, key, w.out, &n_out_s);
+            wave_append(to_dst, key, dst, &n_dst_s);
         }
+        __threadfence_block();
+        __syncthreads();
+        if (tid == 0) {
+            if (!take_all) k_rem_s = k_rem - res[1];
+            n_src_s = take_all ? 0 : n_dst_s;
+        }
+        __syncthreads();
+        uint64_t *t = src;
+        src = dst;
+        dst = t;
     }
-    (void)n_survivors_known;
-    (void)n_surv;
-}
-
-__device__ __forceinline__ void push(uint64_t *buf, int32_t *cnt, uint64_t key) {
-    int32_t j = atomicAdd(cnt, 1);
-    buf[j] = key;
-}
-
-// Level 0 compaction from the scores: digit above the selected one -> out,
-// equal -> cand0.  With take_all every qualifying item goes to out.
-__global__ void __launch_bounds__(256) k_compact_src(const float *score, const uint8_t *flags,
-                                                     int64_t n, uint8_t req, uint8_t forbid,
-                                                     TopkWs w) {
-    TopkCtrl *c = w.ctrl;
-    const int take_all = c->take_all;
-    const int sel = c->sel;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t key;
-        if (!item_key(score, flags, i, req, forbid, key)) continue;
-        const int d = digit_of(key, 0);
-        if (take_all || d > sel) push(w.out, &c->n_out, key);
-        else if (d == sel) push(w.cand0, &c->n_cand[0], key);
-    }
-}
-
-// Later levels: survivors of src -> out (digit above) or dst (digit equal).
-// At the last level (all 64 bits consumed) keys are unique, so digits equal
-// to the selection are taken too.
-__global__ void __launch_bounds__(256) k_compact_cand(int level, int src_i, TopkWs w) {
-    TopkCtrl *c = w.ctrl;
-    const uint64_t *src = src_i ? w.cand1 : w.cand0;
-    uint64_t *dst = src_i ? w.cand0 : w.cand1;
-    int32_t *dcnt = &c->n_cand[src_i ^ 1];
-    const int64_t n = c->n_cand[src_i];
-    const int take_all = c->take_all;
-    const int sel = c->sel;
-    const bool last = level == kLevels - 1;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t key = src[i];
-        const int d = digit_of(key, level);
-        if (take_all || d > sel || (last && d == sel)) push(w.out, &c->n_out, key);
-        else if (d == sel) push(dst, dcnt, key);
-    }
-}
-
-// Reset the destination counter before a level writes into it (also after a
-// take_all, so that later levels see an empty buffer).
-__global__ void k_reset_cnt(TopkWs w, int which) {
-    if (threadIdx.x == 0) w.ctrl->n_cand[which] = 0;
-}
-
-// Sort the chosen keys (descending) and write the results.  1024 threads.
-__global__ void __launch_bounds__(1024) k_topk_final(TopkWs w, int32_t k, int64_t *idx,
-                                                     float *top_score, int32_t *count) {
-    extern __shared__ uint64_t keys[];
-    const int tid = threadIdx.x;
-    int32_t n = w.ctrl->n_out;
-    if (n > k) n = k;   // cannot happen; guards the buffer
-    int32_t P = 1;
-    while (P < n) P <<= 1;
-    for (int i = tid; i < P; i += blockDim.x) keys[i] = i < n ? w.out[i] : 0ull;
+    __threadfence_block();
     __syncthreads();
-    for (int32_t size = 2; size <= P; size <<= 1) {
-        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int32_t i = tid; i < P; i += blockDim.x) {
-                int32_t j = i ^ stride;
-                if (j > i) {
-                    const bool desc = (i & size) == 0;
-                    uint64_t a = keys[i], b = keys[j];
-                    if (desc ? (a < b) : (a > b)) {
-                        keys[i] = b;
-                        keys[j] = a;
-                    }
+    // sort the union of chosen and remaining candidate keys, descending
+    const int32_t no = n_out_s, ns = n_src_s;
+    const int32_t tot = no + ns;   // <= kSortCap here
+    int32_t P = 2;
+    while (P < tot) P <<= 1;
+    for (int i = tid; i < P; i += kRefineThreads)
+        keys[i] = i < no ? w.out[i] : (i < tot ? src[i - no] : 0ull);
+    __syncthreads();
+    const int32_t half = P >> 1;
+    for (int32_t size = 2, lsz = 1; size <= P; size <<= 1, ++lsz) {
+        for (int32_t stride = size >> 1, lst = lsz - 1; stride > 0; stride >>= 1, --lst) {
+            for (int32_t j = tid; j < half; j += kRefineThreads) {
+                const int32_t i = ((j >> lst) << (lst + 1)) | (j & (stride - 1));
+                const int32_t l = i + stride;
+                const bool desc = (i & size) == 0;
+                const uint64_t a = keys[i], b = keys[l];
+                if (desc ? (a < b) : (a > b)) {
+                    keys[i] = b;
+                    keys[l] = a;
                 }
             }
-            __syncthreads();
+            // With a stride below 64 the pairs a wave handles lie inside its
+            // own 128 consecutive elements, so consecutive such stages need
+            // no workgroup barrier; stages with a stride of 64 or more (and
+            // the stage before one) do.
+            const int32_t next = stride > 1 ? stride >> 1 : size;
+            if (stride >= 64 || next >= 64) __syncthreads();
+            else __builtin_amdgcn_wave_barrier();
         }
     }
-    for (int i = tid; i < k; i += blockDim.x) {
+    __syncthreads();
+    const int32_t n = tot < k ? tot : k;
+    for (int i = tid; i < k; i += kRefineThreads) {
         if (i < n) {
-            uint64_t key = keys[i];
+            const uint64_t key = keys[i];
             idx[i] = (int64_t)(0xffffffffu - (uint32_t)(key & 0xffffffffull));
             if (top_score) top_score[i] = unord_f32((uint32_t)(key >> 32));
         } else {
@@ -290,34 +428,16 @@ __global__ void __launch_bounds__(1024) k_topk_final(TopkWs w, int32_t k, int64_
 hipError_t launch_topk(const float *score, const uint8_t *flags, int64_t n, int32_t k,
                        uint8_t req, uint8_t forbid, int64_t *idx, float *top_score,
                        int32_t *count, void *ws, hipStream_t st) {
-    TopkWs w = carve_ws(ws, n, k);
+    const TopkWs w = carve_ws(ws, n, k);
     hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(256), 0, st, w, k);
-    int64_t g = (n + 256 * 8 - 1) / (256 * 8);
+    int64_t g = (n + 256 * kItems - 1) / (256 * kItems);
     if (g < 1) g = 1;
-    if (g > 4096) g = 4096;
-    int64_t gc = (n + 255) / 256;
-    if (gc < 1) gc = 1;
-    if (gc > 2048) gc = 2048;
-    hipLaunchKernelGGL(k_hist_src, dim3((unsigned)g), dim3(256), 0, st, score, flags, n, req,
+    hipLaunchKernelGGL(k_hist0, dim3((unsigned)g), dim3(256), 0, st, score, flags, n, req, forbid,
+                       w);
+    hipLaunchKernelGGL(k_compact0, dim3((unsigned)g), dim3(256), 0, st, score, flags, n, req,
                        forbid, w);
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, st, w, 0, 0, nullptr);
-    hipLaunchKernelGGL(k_compact_src, dim3((unsigned)g), dim3(256), 0, st, score, flags, n,
-                       req, forbid, w);
-    int src = 0;
-    for (int level = 1; level < kLevels; ++level) {
-        const int32_t *cnt = &w.ctrl->n_cand[src];
-        hipLaunchKernelGGL(k_hist_cand, dim3((unsigned)gc), dim3(256), 0, st,
-                           src ? w.cand1 : w.cand0, cnt, level, w);
-        hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, st, w, level, 0, nullptr);
-        hipLaunchKernelGGL(k_reset_cnt, dim3(1), dim3(64), 0, st, w, src ^ 1);
-        hipLaunchKernelGGL(k_compact_cand, dim3((unsigned)gc), dim3(256), 0, st, level, src, w);
-        src ^= 1;
-    }
-    size_t lds = 0;
-    int32_t P = 1;
-    while (P < k) P <<= 1;
-    lds = sizeof(uint64_t) * (size_t)P;
-    hipLaunchKernelGGL(k_topk_final, dim3(1), dim3(1024), lds, st, w, k, idx, top_score, count);
+    hipLaunchKernelGGL(k_refine_sort, dim3(1), dim3(kRefineThreads),
+                       sizeof(uint64_t) * (size_t)kSortCap, st, w, k, idx, top_score, count);
     return hipGetLastError();
 }
 

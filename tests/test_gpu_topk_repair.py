@@ -132,3 +132,23 @@ def test_repair_list_moves_and_count_bound():
     q, a, J, _ = o.repair(inst.p0, blk[cand[:100]], per[cand[:100]])
     assert int(applied.item()) == a
     np.testing.assert_array_equal(to_np(m.get_schedule()), q)
+
+
+def test_state_save_restore_roundtrip():
+    """A saved search state restores the schedule, objective and every move
+    score bit for bit, after a repair has changed them."""
+    from paper_2511_18296_amd.binding import MoveSet, TopK
+    inst = instance("tight")
+    m = gpu_model(inst)
+    snap = m.save_state()
+    sc0, fl0 = [t.clone() for t in m.eval_moves()]
+    obj0 = m.objective()
+    t = TopK(sc0.numel(), 500)
+    idx, _, cnt = t(sc0, fl0)
+    assert int(m.repair(MoveSet(), idx, cnt).item()) > 0
+    assert m.objective()["J"] != obj0["J"]
+    m.restore_state(snap)
+    assert m.objective() == obj0
+    sc1, fl1 = m.eval_moves()
+    assert torch.equal(sc0, sc1) and torch.equal(fl0, fl1)
+    np.testing.assert_array_equal(to_np(m.get_schedule()), inst.p0)
