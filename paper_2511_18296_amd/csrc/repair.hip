@@ -114,7 +114,7 @@ __host__ __device__ inline RepairLayout repair_layout(int32_t S, int32_t T, int3
     L.hval = put(H);
     L.buf[0] = put(rb * B);
     L.buf[1] = put(rb * B);
-    L.res = put(sizeof(double) * 3 * kWaves + sizeof(int32_t) * 2 * kWaves + 64);
+    L.res = put(sizeof(double) * 4 * kWaves + sizeof(int32_t) * kWaves + 8 + 64);
     L.total = off;
     L.B = B;
     return L;
@@ -208,9 +208,13 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
     int32_t *hkey = (int32_t *)(lds + Lo.hkey);
     int8_t *hval = (int8_t *)(lds + Lo.hval);
     char *bufp[2] = {lds + Lo.buf[0], lds + Lo.buf[1]};
-    double *res = (double *)(lds + Lo.res);      // c of each wave's candidate
-    double *stat = res + kWaves;                 // mu, var, sigma
-    int32_t *ires = (int32_t *)(res + 2 * kWaves);   // accept flags, current periods
+    // per wave: mu, var, sigma after its candidate's move; then mu, var,
+    // sigma of the current state; then the wave's current period of the
+    // block and one accept byte per wave
+    double *res = (double *)(lds + Lo.res);
+    double *stat = res + 3 * kWaves;
+    int32_t *ipb = (int32_t *)(stat + 3);
+    uint8_t *acc = (uint8_t *)(ipb + kWaves);
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -309,7 +313,7 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
                     __ballot(key >= 0 && ((lane >= 1 && lane <= 5 && cur > t) ||
                                           (lane >= 6 && lane <= 10 && t > cur))) != 0ull;
                 bool eligible = e.b >= 0 && !moved && !bad_prec && t != pb;
-                double score = -1.0, c = 0.0;
+                double score = -1.0, mu1 = 0.0, var1 = 0.0, sig1 = 0.0;
                 if (eligible) {
                     const double mu = stat[0], var = stat[1], sigma = stat[2];
                     const double ton = e.ton;
@@ -331,11 +335,14 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
                             }
                         }
                     }
-                    c = wave_sum(cp) / S;
+                    const double c = wave_sum(cp) / S;
                     pen = wave_sum(pen);
                     viol = __ballot(viol) != 0ull;
                     const double dvar = 2.0 * dd * c + dd * dd * e.Vb;
-                    const double sp = sqrt(fmax(var + dvar, 0.0));
+                    var1 = fmax(var + dvar, 0.0);
+                    const double sp = sqrt(var1);
+                    sig1 = sp;
+                    mu1 = mu + dd * e.mb;
                     const double den = sp + sigma;
                     const double dsig = den > 0.0 ? dvar / den : 0.0;
                     const double dR = dd * e.mb - m.lambda * dsig;
@@ -351,25 +358,26 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
                     if (hard && !(mine_ok && !viol)) eligible = false;
                 }
                 if (lane == 0) {
-                    ires[wave] = (eligible && score > 0.0) ? 1 : 0;
-                    ires[kWaves + wave] = pb;
-                    res[wave] = c;
+                    acc[wave] = (eligible && score > 0.0) ? 1 : 0;
+                    ipb[wave] = pb;
+                    res[3 * wave] = mu1;
+                    res[3 * wave + 1] = var1;
+                    res[3 * wave + 2] = sig1;
                 }
+            } else if (lane == 0) {
+                acc[wave] = 0;
             }
             __syncthreads();
-            // ---- the first accepted candidate of the round, if any
-            int32_t r = ne;
-            for (int w = 0; w < ne; ++w)
-                if (ires[w]) {
-                    r = w;
-                    break;
-                }
+            // ---- the first accepted candidate of the round, if any: one
+            // byte per wave, read as one 64-bit word
+            const uint64_t am = *(const volatile uint64_t *)acc & 0x0101010101010101ull;
+            const int32_t r = am ? (__builtin_ctzll(am) >> 3) : ne;
             if (r < ne) {
                 const char *rp = bb + (size_t)(pos + r - c0) * rb;
                 const CandHdr &e = *(const CandHdr *)rp;
                 const float *vb = (const float *)(rp + sizeof(CandHdr));
                 const uint32_t *ob = (const uint32_t *)(vb + S);
-                const int32_t t = e.t, pb = ires[kWaves + r];
+                const int32_t t = e.t, pb = ipb[r];
                 const double dd = dl[t] - dl[pb];
                 const double ton = e.ton;
                 for (int32_t s = tid; s < S; s += kThreads) {
@@ -387,11 +395,8 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
                     while (hkey[hs] >= 0) hs = (hs + 1) & (uint32_t)(H - 1);
                     hkey[hs] = e.b;
                     hval[hs] = (int8_t)t;
-                    const double c = res[r];
-                    stat[0] += dd * e.mb;
-                    stat[1] = fmax(stat[1] + 2.0 * dd * c + dd * dd * e.Vb, 0.0);
-                    stat[2] = sqrt(stat[1]);
                 }
+                if (tid >= 64 && tid < 67) stat[tid - 64] = res[3 * r + tid - 64];
                 ++applied;
                 pos += r + 1;
             } else {
