@@ -59,6 +59,89 @@ def cpu_baseline(inst, k):
                       f"top-{k}, repair) of the same instance, {dt:.2f} s"}
 
 
+def batch_bytes(insts, moves):
+    """Algorithmic HBM bytes of one batched launch: per model v (4SN), ore
+    words (4*ceil(S/32)*N), per-block scalars read once (p, ton32, ton64,
+    m_b, V_b: 21N), the move list (5M) and scores + flags (5M)."""
+    tot = 0
+    for inst, (blk, _) in zip(insts, moves):
+        W = (inst.S + 31) // 32
+        tot += 4 * inst.S * inst.N + 4 * W * inst.N + 21 * inst.N + 10 * len(blk)
+    return tot
+
+
+def _gen_batch_member(spec):
+    import mpsgen
+    inst = mpsgen.make_instance(spec["nx"], spec["ny"], spec["nz"], spec["S"], spec["T"],
+                                spec["r"], spec["seed"])
+    blk, per = mpsgen.random_moves(inst.N, inst.T, spec["M"], spec["seed"] + 1000)
+    return inst, (blk, per)
+
+
+def batched_leg(steps, k=256):
+    """64 models of mixed sizes with 10k-300k random moves each in one
+    persistent launch (autotuned), replayed as a HIP graph."""
+    import mpsgen
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_2511_18296_amd.binding import Batch, Model
+    specs = mpsgen.batched_specs()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        res = list(ex.map(_gen_batch_member, specs))
+    insts = [r[0] for r in res]
+    moves = [r[1] for r in res]
+    models = [Model.from_instance(i) for i in insts]
+    dev = [(torch.from_numpy(b).cuda(), torch.from_numpy(p).cuda()) for b, p in moves]
+    batch = Batch(models, dev, k)
+    tuned_us = batch.autotune(reps=3)
+    for _ in range(3):
+        batch.graph_launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        batch.graph_launch()
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / steps * 1e-3
+    err = batch.error()
+    B = batch_bytes(insts, moves)
+    evals = sum(len(b) * i.S for i, (b, _) in zip(insts, moves))
+    tun = {}
+    for i, inst in enumerate(insts):
+        tun.setdefault(f"S<={32 if inst.S <= 32 else 64 if inst.S <= 64 else 128 if inst.S <= 128 else 'max'}",
+                       batch.tuning(i))
+    return {"instances": len(insts), "blocks": int(sum(i.N for i in insts)),
+            "moves": int(sum(len(b) for b, _ in moves)), "topk_per_instance": k,
+            "us_per_launch": t * 1e6, "autotune_median_us": tuned_us,
+            "move_scenario_evals_per_s": evals / t, "algorithmic_bytes": B,
+            "achieved_GBs": B / t / 1e9, "frac_of_hbm_peak": B / t / 1e9 / HBM_PEAK_GBS,
+            "graph_replays_timed": steps, "error_word": err, "tuning": tun}
+
+
+RELAX = (100.0 / (2 * 15600), 100.0 / (2 * 15600), 100.0 * 15600)
+
+
+def search_leg(model, seed_state, k):
+    """Gradient-ranked search vs exhaustive search from the same seeded schedule."""
+    import torch
+    out = {}
+    for name, mode in (("exhaustive", 0), ("gradient_ranked", 1)):
+        model.restore_state(seed_state)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = model.search(mode, k, RELAX, max_iter=10000)
+        dt = time.perf_counter() - t0
+        out[name] = {"J": st["J"], "iterations": int(st["iterations"]),
+                     "exact_evaluations": int(st["evaluations"]),
+                     "applied": int(st["applied"]), "seconds": dt}
+    JE, JG = out["exhaustive"]["J"], out["gradient_ranked"]["J"]
+    out["rel_diff"] = abs(JG - JE) / abs(JE)
+    out["relax_weights"] = list(RELAX)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +150,8 @@ def main():
     ap.add_argument("--copies", type=int, default=8)
     ap.add_argument("--k", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-search", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -163,6 +248,16 @@ def main():
         "eval_move_scenario_evals_per_s": M * S / t_eval,
         "final_J": [o["J"] for o in objs],
     }
+    if not args.no_search:
+        log("search comparison (exhaustive vs gradient-ranked) ...")
+        out["search"] = search_leg(models[0], seeds[0], args.k)
+        log(f"search: {json.dumps(out['search'])}")
+    del models, seeds
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        log("batched: generating 64 instances ...")
+        out["batched"] = batched_leg(20)
+        log(f"batched: {json.dumps(out['batched'])}")
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(inst, args.k)

@@ -69,6 +69,8 @@ enum {
 #define MPS_MAX_PERIODS 126          /* T; periods are int8 with T = never */
 #define MPS_MAX_SCENARIOS 4096       /* S */
 #define MPS_MAX_TOPK 8192            /* k of mps_topk / mps_rank_moves */
+#define MPS_MAX_BATCH_TOPK 1024      /* k of a batch (per model) */
+#define MPS_MAX_BATCH 4096           /* models in one batch */
 
 typedef struct mps_model mps_model;
 
@@ -264,6 +266,85 @@ typedef struct {
 
 mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_params *rp,
                       int32_t max_iter, mps_search_stats *out, void *stream);
+
+/* ---- batched evaluation ---------------------------------------------------
+ * Many models (for instance, one schedule per individual of the population
+ * the metaheuristic of Alg. 2 keeps), each with its own list of candidate
+ * moves of any length, are evaluated in ONE persistent kernel launch that
+ * ends with every model's exact top k.  The launch is a queue of work items:
+ * per-block passes over each model's block values, then chunks of each
+ * model's moves, then each model's top-k selection (largest model first);
+ * workgroups that stay resident for the whole launch take items from one
+ * atomic counter.  Results equal those of mps_eval_moves on each model's
+ * list followed by mps_topk with the same k, require and forbid.
+ *
+ * Tuning: how the work of one model is cut into items, set per model (the
+ * autotuner sets it per class of models with the same S range). */
+typedef struct {
+    int32_t tiles_per_item;   /* 64-block tiles per block-pass item, 1..64 */
+    int32_t moves_per_item;   /* moves per move item: a multiple of 512 in 512..65536 */
+    int32_t rows;             /* block values each lane has in flight: 8, 16 or 32 */
+    int32_t reserved;         /* must be 0 */
+} mps_tuning;
+
+/* One model's part of a batch (device pointers, caller-owned). */
+typedef struct {
+    const int32_t *block;     /* [n] moved block */
+    const int8_t *period;     /* [n] destination period 0..T */
+    int64_t n;                /* 0 <= n < 2^31 */
+    float *score;             /* [n] out: as mps_eval_moves */
+    uint8_t *flags;           /* [n] out */
+    int64_t *top_idx;         /* [k] out: positions in this model's list, -1 past the count */
+    float *top_score;         /* [k] out or NULL */
+    int32_t *top_count;       /* out: device int32 */
+} mps_batch_item;
+
+typedef struct mps_batch mps_batch;
+
+/* Build a batch over n_models models (all on one device; they must outlive
+ * the batch) and their move lists.  Allocates the descriptor table, the work
+ * queue and the counters; the tuning of each model comes from the process
+ * tuning cache (filled by mps_batch_autotune) or from defaults.  Two batches
+ * that share a model must not run at the same time (they share its block
+ * workspace), nor may a batch run concurrently with mps_eval_moves in list
+ * mode on one of its models.  Synchronises; not capturable.
+ * 1 <= n_models <= MPS_MAX_BATCH, 1 <= k <= MPS_MAX_BATCH_TOPK. */
+mps_status mps_batch_create(mps_model *const *models, const mps_batch_item *items,
+                            int32_t n_models, int32_t k, uint8_t require, uint8_t forbid,
+                            mps_batch **out);
+mps_status mps_batch_destroy(mps_batch *b);
+
+/* Set the tuning of model i (or of every model when i = -1), or read it.
+ * Rebuilds the work queue (synchronises).  Invalid values: MPS_E_INVALID_ARG. */
+mps_status mps_batch_set_tuning(mps_batch *b, int32_t i, const mps_tuning *t);
+mps_status mps_batch_get_tuning(const mps_batch *b, int32_t i, mps_tuning *t);
+
+/* Resident workgroups of the persistent launch: 0 = as many as fit on the
+ * device at once (the default), otherwise 1 .. that number. */
+mps_status mps_batch_set_workgroups(mps_batch *b, int32_t n);
+
+/* Enqueue the batch on `stream`: one small clearing kernel (no memset) and
+ * the persistent kernel.  Capturable.  Calls on one batch must not overlap. */
+mps_status mps_batch_run(mps_batch *b, void *stream);
+
+/* The same work replayed as a HIP graph: the first call captures
+ * mps_batch_run into a graph (on a stream of the batch's own) and
+ * instantiates it; every call then launches that graph on `stream`.  A
+ * tuning or workgroup change drops the graph.  Not capturable itself. */
+mps_status mps_batch_graph_launch(mps_batch *b, void *stream);
+
+/* Autotune: for each class of models (S <= 32, <= 64, <= 128, > 128) try
+ * the candidate values of rows, tiles_per_item and moves_per_item in turn
+ * (coordinate descent), then the workgroup count, timing `reps` runs of the
+ * whole batch per candidate with HIP events (median); keep the fastest,
+ * apply it and store it in the process tuning cache.  The batch's outputs
+ * hold the results of its last timed run.  Synchronises; not capturable.
+ * *best_us (may be NULL) receives the median time of the chosen tuning. */
+mps_status mps_batch_autotune(mps_batch *b, int32_t reps, double *best_us, void *stream);
+
+/* Error word of the last run (synchronises `stream`): 0, or 1 when a wait of
+ * the persistent kernel on a dependency ran past its bound. */
+mps_status mps_batch_error(mps_batch *b, int32_t *err, void *stream);
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(PKG, "libmps.so")
 
 PREC_OK, MINE_OK, PROC_OK, NOOP, BAD = 1, 2, 4, 8, 16
 MAX_PERIODS, MAX_SCENARIOS, MAX_TOPK = 126, 4096, 8192
+MAX_BATCH_TOPK, MAX_BATCH = 1024, 4096
 
 STATUS = {0: "MPS_OK", 1: "MPS_E_INVALID_ARG", 2: "MPS_E_OUT_OF_MEMORY",
           3: "MPS_E_DEVICE", 4: "MPS_E_INFEASIBLE", 5: "MPS_E_NOT_CAPTURABLE",
@@ -59,6 +60,17 @@ class SearchStats(C.Structure):
                 ("applied", C.c_int64), ("J", C.c_double)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("tiles_per_item", C.c_int32), ("moves_per_item", C.c_int32),
+                ("rows", C.c_int32), ("reserved", C.c_int32)]
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("block", C.c_void_p), ("period", C.c_void_p), ("n", C.c_int64),
+                ("score", C.c_void_p), ("flags", C.c_void_p), ("top_idx", C.c_void_p),
+                ("top_score", C.c_void_p), ("top_count", C.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -90,6 +102,15 @@ def _load():
         "mps_state_bytes": ([vp], C.c_size_t),
         "mps_state_save": ([vp, vp, vp], st),
         "mps_state_restore": ([vp, vp, vp], st),
+        "mps_batch_create": ([vp, vp, i32, i32, C.c_uint8, C.c_uint8, vp], st),
+        "mps_batch_destroy": ([vp], st),
+        "mps_batch_set_tuning": ([vp, i32, vp], st),
+        "mps_batch_get_tuning": ([vp, i32, vp], st),
+        "mps_batch_set_workgroups": ([vp, i32], st),
+        "mps_batch_run": ([vp, vp], st),
+        "mps_batch_graph_launch": ([vp, vp], st),
+        "mps_batch_autotune": ([vp, i32, vp, vp], st),
+        "mps_batch_error": ([vp, vp, vp], st),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -107,7 +128,9 @@ EXPORTS = ("mps_last_error", "mps_version", "mps_device_count", "mps_build_model
            "mps_eval_moves", "mps_topk_ws_bytes", "mps_topk", "mps_repair",
            "mps_relaxed_saved_bytes", "mps_relaxed_fwd", "mps_relaxed_bwd",
            "mps_rank_ws_bytes", "mps_rank_moves", "mps_search", "mps_state_bytes",
-           "mps_state_save", "mps_state_restore")
+           "mps_state_save", "mps_state_restore", "mps_batch_create", "mps_batch_destroy",
+           "mps_batch_set_tuning", "mps_batch_get_tuning", "mps_batch_set_workgroups",
+           "mps_batch_run", "mps_batch_graph_launch", "mps_batch_autotune", "mps_batch_error")
 
 
 def check(status: int):
@@ -370,3 +393,83 @@ def topk(score, flags, k, require=PREC_OK, forbid=NOOP | BAD, stream=None):
     idx, sc, cnt = t(score, flags, require, forbid, stream)
     c = int(cnt.item())
     return idx[:c].clone(), sc[:c].clone()
+
+
+class Batch:
+    """Many models with their own move lists, evaluated in one persistent
+    launch that ends with each model's top k (mps_batch_*).
+
+    moves[i] is (block int32 [n_i], period int8 [n_i]) on the GPU.  The
+    batch owns the output tensors: score[i], flags[i], top_idx[i],
+    top_score[i], top_count[i]."""
+
+    def __init__(self, models, moves, k, require=PREC_OK, forbid=NOOP | BAD):
+        if len(models) != len(moves):
+            raise ValueError("one move list per model")
+        self.models, self.k = list(models), int(k)
+        dev = models[0].device
+        self.block, self.period = [], []
+        self.score, self.flags, self.top_idx, self.top_score, self.top_count = [], [], [], [], []
+        items = (BatchItem * len(models))()
+        for i, (blk, per) in enumerate(moves):
+            _dev(blk, torch.int32, None, "block")
+            _dev(per, torch.int8, blk.shape, "period")
+            n = int(blk.shape[0])
+            self.block.append(blk)
+            self.period.append(per)
+            self.score.append(torch.empty(n, dtype=torch.float32, device=dev))
+            self.flags.append(torch.empty(n, dtype=torch.uint8, device=dev))
+            self.top_idx.append(torch.empty(self.k, dtype=torch.int64, device=dev))
+            self.top_score.append(torch.empty(self.k, dtype=torch.float32, device=dev))
+            self.top_count.append(torch.zeros(1, dtype=torch.int32, device=dev))
+            items[i] = BatchItem(blk.data_ptr() if n else None, per.data_ptr() if n else None, n,
+                                 self.score[i].data_ptr() if n else None,
+                                 self.flags[i].data_ptr() if n else None,
+                                 self.top_idx[i].data_ptr(), self.top_score[i].data_ptr(),
+                                 self.top_count[i].data_ptr())
+        hs = (C.c_void_p * len(models))(*[m.h.value for m in models])
+        h = C.c_void_p()
+        check(lib.mps_batch_create(hs, items, len(models), self.k, require, forbid,
+                                   C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(lib.mps_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, tiles_per_item, moves_per_item, rows, i=-1):
+        t = Tuning(tiles_per_item, moves_per_item, rows, 0)
+        check(lib.mps_batch_set_tuning(self.h, int(i), C.byref(t)))
+
+    def tuning(self, i) -> dict:
+        t = Tuning()
+        check(lib.mps_batch_get_tuning(self.h, int(i), C.byref(t)))
+        return dict(tiles_per_item=t.tiles_per_item, moves_per_item=t.moves_per_item,
+                    rows=t.rows)
+
+    def set_workgroups(self, n):
+        check(lib.mps_batch_set_workgroups(self.h, int(n)))
+
+    def run(self, stream=None):
+        check(lib.mps_batch_run(self.h, _stream(stream)))
+
+    def graph_launch(self, stream=None):
+        check(lib.mps_batch_graph_launch(self.h, _stream(stream)))
+
+    def autotune(self, reps=5, stream=None) -> float:
+        us = C.c_double(0.0)
+        check(lib.mps_batch_autotune(self.h, int(reps), C.byref(us), _stream(stream)))
+        return us.value
+
+    def error(self, stream=None) -> int:
+        e = C.c_int32(0)
+        check(lib.mps_batch_error(self.h, C.byref(e), _stream(stream)))
+        return e.value
+

@@ -6,9 +6,13 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "internal.h"
 
 using namespace mps;
@@ -690,6 +694,393 @@ mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_par
         out->J = obj.J;
     }
     return MPS_OK;
+}
+
+}  // extern "C"
+
+// ---- batches -------------------------------------------------------------------
+namespace {
+
+std::mutex g_tune_mu;
+std::map<int, mps_tuning> g_tune_cache;   // S class -> tuning chosen by the autotuner
+
+int tune_class(int32_t S) { return S <= 32 ? 0 : S <= 64 ? 1 : S <= 128 ? 2 : 3; }
+
+mps_tuning default_tuning(int32_t S) {
+    mps_tuning t{};
+    t.tiles_per_item = 2;
+    t.moves_per_item = 4096;
+    t.rows = S <= 64 ? 8 : S <= 128 ? 16 : 32;
+    return t;
+}
+
+bool tuning_ok(const mps_tuning &t) {
+    return t.reserved == 0 && t.tiles_per_item >= 1 && t.tiles_per_item <= 64 &&
+           t.moves_per_item >= 512 && t.moves_per_item <= 65536 && t.moves_per_item % 512 == 0 &&
+           (t.rows == 8 || t.rows == 16 || t.rows == 32);
+}
+
+}  // namespace
+
+struct mps_batch {
+    int device = 0;
+    int32_t n = 0, k = 0;
+    uint8_t req = 0, forbid = 0;
+    std::vector<mps_model *> models;
+    std::vector<mps_batch_item> items;
+    std::vector<mps_tuning> tune;
+    std::vector<int32_t> order;   // models by decreasing block-value bytes
+    BatchInst *d_insts = nullptr;
+    int2 *d_items = nullptr;
+    uint32_t *d_ctl = nullptr;
+    int64_t max_items = 0;
+    int32_t n_items = 0;
+    size_t lds = 0;
+    int per_cu = 1, cus = 1, workgroups = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    void drop_graph() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    int grid() const {
+        const int full = per_cu * cus;
+        int g = workgroups > 0 ? std::min(workgroups, full) : full;
+        if ((int64_t)g > n_items) g = (int)n_items;
+        return g > 0 ? g : 1;
+    }
+    BatchLaunch launch() const {
+        BatchLaunch bl;
+        bl.insts = d_insts;
+        bl.items = d_items;
+        bl.n_items = n_items;
+        bl.n_inst = n;
+        bl.ctl = d_ctl;
+        bl.k = k;
+        bl.req = req;
+        bl.forbid = forbid;
+        bl.grid = grid();
+        bl.lds_bytes = lds;
+        return bl;
+    }
+    // Descriptors and work queue from the current tuning (synchronous copies).
+    mps_status rebuild() {
+        std::vector<BatchInst> hi(n);
+        for (int32_t i = 0; i < n; ++i) {
+            const mps_batch_item &it = items[i];
+            BatchInst &I = hi[i];
+            I.m = models[i]->d;
+            I.blk = it.block;
+            I.per = it.period;
+            I.n = it.n;
+            I.score = it.score;
+            I.flags = it.flags;
+            I.top_idx = it.top_idx;
+            I.top_score = it.top_score;
+            I.top_count = it.top_count;
+            I.n_tiles = (int32_t)((I.m.N + 63) / 64);
+            I.tiles_per_item = tune[i].tiles_per_item;
+            I.n1 = it.n > 0 ? (I.n_tiles + I.tiles_per_item - 1) / I.tiles_per_item : 0;
+            I.moves_per_item = tune[i].moves_per_item;
+            I.n2 = (int32_t)((it.n + I.moves_per_item - 1) / I.moves_per_item);
+            I.rows = tune[i].rows;
+        }
+        std::vector<int2> q;
+        q.reserve((size_t)max_items);
+        for (int32_t i : order)
+            for (int32_t j = 0; j < hi[i].n1; ++j) q.push_back(make_int2(i, j));
+        for (int32_t i : order)
+            for (int32_t j = 0; j < hi[i].n2; ++j) q.push_back(make_int2(i, hi[i].n1 + j));
+        for (int32_t i : order) q.push_back(make_int2(i, hi[i].n1 + hi[i].n2));
+        if ((int64_t)q.size() > max_items) return fail(MPS_E_INTERNAL, "work queue overflow");
+        DeviceGuard g(device);
+        hipError_t e = hipMemcpy(d_insts, hi.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(d_items, q.data(), sizeof(int2) * q.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return dev_fail(e, "batch descriptors");
+        n_items = (int32_t)q.size();
+        drop_graph();
+        return MPS_OK;
+    }
+    ~mps_batch() {
+        DeviceGuard g(device);
+        drop_graph();
+        if (cap) hipStreamDestroy(cap);
+        hipFree(d_insts);
+        hipFree(d_items);
+        hipFree(d_ctl);
+    }
+};
+
+extern "C" {
+
+mps_status mps_batch_create(mps_model *const *models, const mps_batch_item *items,
+                            int32_t n_models, int32_t k, uint8_t require, uint8_t forbid,
+                            mps_batch **out) {
+    if (!out) return fail(MPS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!models || !items) return fail(MPS_E_INVALID_ARG, "models and items are required");
+    if (n_models < 1 || n_models > MPS_MAX_BATCH)
+        return fail(MPS_E_INVALID_ARG, "n_models must be in 1..%d", MPS_MAX_BATCH);
+    if (k < 1 || k > MPS_MAX_BATCH_TOPK)
+        return fail(MPS_E_INVALID_ARG, "k must be in 1..%d (got %d)", MPS_MAX_BATCH_TOPK, k);
+    size_t lds = 0;
+    int64_t max_items = 0;
+    for (int32_t i = 0; i < n_models; ++i) {
+        const mps_model *m = models[i];
+        const mps_batch_item &it = items[i];
+        if (!m) return fail(MPS_E_INVALID_ARG, "model %d is NULL", i);
+        if (m->device != models[0]->device)
+            return fail(MPS_E_INVALID_ARG, "model %d is on another device", i);
+        if (it.n < 0 || it.n >= ((int64_t)1 << 31))
+            return fail(MPS_E_INVALID_ARG, "item %d: n = %lld out of range", i, (long long)it.n);
+        if (it.n > 0 && (!it.block || !it.period || !it.score || !it.flags))
+            return fail(MPS_E_INVALID_ARG, "item %d: block, period, score, flags are required", i);
+        if (!it.top_idx || !it.top_count)
+            return fail(MPS_E_INVALID_ARG, "item %d: top_idx and top_count are required", i);
+        lds = std::max(lds, batch_lds_bytes(m->d));
+        max_items += (m->d.N + 63) / 64 + (it.n + 511) / 512 + 1;
+    }
+    if (lds > (size_t)models[0]->max_lds)
+        return fail(MPS_E_INVALID_ARG, "batch needs %zu bytes of LDS, device allows %d", lds,
+                    models[0]->max_lds);
+    if (max_items >= ((int64_t)1 << 31)) return fail(MPS_E_INVALID_ARG, "batch too large");
+    mps_batch *b = new mps_batch;
+    b->device = models[0]->device;
+    b->n = n_models;
+    b->k = k;
+    b->req = require;
+    b->forbid = forbid;
+    b->models.assign(models, models + n_models);
+    b->items.assign(items, items + n_models);
+    b->lds = lds;
+    b->max_items = max_items;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (int32_t i = 0; i < n_models; ++i) {
+            auto f = g_tune_cache.find(tune_class(models[i]->d.S));
+            b->tune.push_back(f != g_tune_cache.end() ? f->second : default_tuning(models[i]->d.S));
+        }
+    }
+    b->order.resize(n_models);
+    for (int32_t i = 0; i < n_models; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t a, int32_t c) {
+        const DevModel &x = models[a]->d, &y = models[c]->d;
+        return (int64_t)x.S * x.N > (int64_t)y.S * y.N;
+    });
+    DeviceGuard g(b->device);
+    hipError_t e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (e == hipSuccess) e = batch_occupancy(lds, &b->per_cu);
+    if (e == hipSuccess && b->per_cu < 1) e = hipErrorInvalidConfiguration;
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_insts, sizeof(BatchInst) * n_models);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_items, sizeof(int2) * (size_t)max_items);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->d_ctl, sizeof(uint32_t) * (size_t)batch_ctl_words(n_models));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return dev_fail(e, "batch create");
+    }
+    mps_status st = b->rebuild();
+    if (st != MPS_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return MPS_OK;
+}
+
+mps_status mps_batch_destroy(mps_batch *b) {
+    if (!b) return fail(MPS_E_INVALID_ARG, "batch is NULL");
+    {
+        DeviceGuard g(b->device);
+        hipDeviceSynchronize();
+    }
+    delete b;
+    return MPS_OK;
+}
+
+mps_status mps_batch_set_tuning(mps_batch *b, int32_t i, const mps_tuning *t) {
+    if (!b || !t) return fail(MPS_E_INVALID_ARG, "batch and tuning are required");
+    if (i < -1 || i >= b->n) return fail(MPS_E_INVALID_ARG, "model index %d out of range", i);
+    if (!tuning_ok(*t))
+        return fail(MPS_E_INVALID_ARG,
+                    "tuning out of range (tiles_per_item 1..64, moves_per_item a multiple of "
+                    "512 in 512..65536, rows 8/16/32, reserved 0)");
+    if (i < 0)
+        std::fill(b->tune.begin(), b->tune.end(), *t);
+    else
+        b->tune[i] = *t;
+    return b->rebuild();
+}
+
+mps_status mps_batch_get_tuning(const mps_batch *b, int32_t i, mps_tuning *t) {
+    if (!b || !t) return fail(MPS_E_INVALID_ARG, "batch and tuning are required");
+    if (i < 0 || i >= b->n) return fail(MPS_E_INVALID_ARG, "model index %d out of range", i);
+    *t = b->tune[i];
+    return MPS_OK;
+}
+
+mps_status mps_batch_set_workgroups(mps_batch *b, int32_t n) {
+    if (!b) return fail(MPS_E_INVALID_ARG, "batch is NULL");
+    if (n < 0 || n > b->per_cu * b->cus)
+        return fail(MPS_E_INVALID_ARG, "workgroups must be in 0..%d", b->per_cu * b->cus);
+    b->workgroups = n;
+    b->drop_graph();
+    return MPS_OK;
+}
+
+mps_status mps_batch_run(mps_batch *b, void *stream) {
+    if (!b) return fail(MPS_E_INVALID_ARG, "batch is NULL");
+    DeviceGuard g(b->device);
+    hipError_t e = launch_batch(b->launch(), (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "batch run");
+}
+
+mps_status mps_batch_graph_launch(mps_batch *b, void *stream) {
+    if (!b) return fail(MPS_E_INVALID_ARG, "batch is NULL");
+    hipStream_t hs = (hipStream_t)stream;
+    if (capturing(hs)) return fail(MPS_E_NOT_CAPTURABLE, "mps_batch_graph_launch during capture");
+    DeviceGuard g(b->device);
+    if (!b->exec) {
+        hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return dev_fail(e, "begin capture");
+        const hipError_t el = launch_batch(b->launch(), b->cap);
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(b->cap, &gr);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (gr) hipGraphDestroy(gr);
+            return dev_fail(el != hipSuccess ? el : e, "capture batch");
+        }
+        b->graph = gr;
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            b->drop_graph();
+            return dev_fail(e, "instantiate batch graph");
+        }
+    }
+    hipError_t e = hipGraphLaunch(b->exec, hs);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "launch batch graph");
+}
+
+mps_status mps_batch_error(mps_batch *b, int32_t *err, void *stream) {
+    if (!b || !err) return fail(MPS_E_INVALID_ARG, "batch and err are required");
+    hipStream_t hs = (hipStream_t)stream;
+    if (capturing(hs)) return fail(MPS_E_NOT_CAPTURABLE, "mps_batch_error during capture");
+    DeviceGuard g(b->device);
+    uint32_t w = 0;
+    hipError_t e = hipMemcpyAsync(&w, b->d_ctl + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return dev_fail(e, "batch error word");
+    *err = (int32_t)w;
+    return MPS_OK;
+}
+
+mps_status mps_batch_autotune(mps_batch *b, int32_t reps, double *best_us, void *stream) {
+    if (!b) return fail(MPS_E_INVALID_ARG, "batch is NULL");
+    if (reps < 1 || reps > 1000) return fail(MPS_E_INVALID_ARG, "reps must be in 1..1000");
+    hipStream_t hs = (hipStream_t)stream;
+    if (capturing(hs)) return fail(MPS_E_NOT_CAPTURABLE, "mps_batch_autotune during capture");
+    DeviceGuard g(b->device);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return dev_fail(hipGetLastError(), "autotune events");
+    }
+    std::vector<float> ts(reps);
+    // median time of `reps` runs (after one untimed run), in microseconds
+    auto measure = [&](double &us) -> mps_status {
+        hipError_t e = launch_batch(b->launch(), hs);
+        for (int32_t r = 0; r < reps && e == hipSuccess; ++r) {
+            e = hipEventRecord(e0, hs);
+            if (e == hipSuccess) e = launch_batch(b->launch(), hs);
+            if (e == hipSuccess) e = hipEventRecord(e1, hs);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ts[r], e0, e1);
+        }
+        if (e != hipSuccess) return dev_fail(e, "autotune run");
+        std::vector<float> t2 = ts;
+        std::nth_element(t2.begin(), t2.begin() + reps / 2, t2.end());
+        us = 1e3 * t2[reps / 2];
+        return MPS_OK;
+    };
+    mps_status st = MPS_OK;
+    double best = 0.0;
+    std::vector<int> classes;
+    for (int32_t i = 0; i < b->n; ++i) classes.push_back(tune_class(b->models[i]->d.S));
+    std::sort(classes.begin(), classes.end());
+    classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+    if ((st = measure(best)) != MPS_OK) goto done;
+    for (int c : classes) {
+        // one parameter at a time, the others held at their current best
+        for (int param = 0; param < 3; ++param) {
+            static const int kRows[] = {8, 16, 32};
+            static const int kTiles[] = {1, 2, 4, 8};
+            static const int kMoves[] = {1024, 2048, 4096, 8192, 16384};
+            const int *vals = param == 0 ? kRows : param == 1 ? kTiles : kMoves;
+            const int nv = param == 0 ? 3 : param == 1 ? 4 : 5;
+            for (int v = 0; v < nv; ++v) {
+                std::vector<mps_tuning> saved = b->tune;
+                bool changed = false;
+                for (int32_t i = 0; i < b->n; ++i) {
+                    if (tune_class(b->models[i]->d.S) != c) continue;
+                    mps_tuning &t = b->tune[i];
+                    int &field = param == 0 ? t.rows : param == 1 ? t.tiles_per_item
+                                                                  : t.moves_per_item;
+                    if (field != vals[v]) changed = true;
+                    field = vals[v];
+                }
+                if (!changed) continue;
+                double us = 0.0;
+                if ((st = b->rebuild()) != MPS_OK || (st = measure(us)) != MPS_OK) goto done;
+                if (us < best) {
+                    best = us;
+                } else {
+                    b->tune = saved;
+                    if ((st = b->rebuild()) != MPS_OK) goto done;
+                }
+            }
+        }
+    }
+    {
+        const int full = b->per_cu * b->cus;
+        const int cands[] = {b->cus, 2 * b->cus, 0};
+        int best_wg = b->workgroups;
+        for (int wg : cands) {
+            if (wg > full || wg == b->workgroups) continue;
+            const int old = b->workgroups;
+            b->workgroups = wg;
+            b->drop_graph();
+            double us = 0.0;
+            if ((st = measure(us)) != MPS_OK) goto done;
+            if (us < best) {
+                best = us;
+                best_wg = wg;
+            }
+            b->workgroups = old;
+        }
+        b->workgroups = best_wg;
+        b->drop_graph();
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (int32_t i = 0; i < b->n; ++i) g_tune_cache[tune_class(b->models[i]->d.S)] = b->tune[i];
+    }
+    // leave the outputs those of the chosen tuning
+    {
+        double us = 0.0;
+        st = measure(us);
+    }
+done:
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st == MPS_OK && best_us) *best_us = best;
+    return st;
 }
 
 }  // extern "C"

@@ -1,0 +1,389 @@
+// batch.hip -- many models with uneven move lists evaluated in ONE persistent
+// launch, ending with each model's exact top k (the candidate evaluation of
+// Alg. 5 applied to a population of schedules at once, the shape of work the
+// metaheuristic of Alg. 2 produces: one schedule per individual, each with its
+// own candidate list).
+//
+// Work items, in queue order:
+//   phase 1 (model i, item j): the per-block quantities of the list pass
+//           (c_b, removal term, precedence window) for tiles [j*tpi, j*tpi+tpi)
+//           of 64 blocks, written to the model's block workspace;
+//   phase 2 (model i, item j): moves [j*mpi, j*mpi+mpi) of model i scored and
+//           flagged, and the top 12 bits of their top-k keys counted into the
+//           model's level-0 histogram;
+//   phase 3 (model i): the exact top k of model i, starting from that
+//           histogram (the key and order of mps_topk).
+// Phase-1 items come first, largest model first, then the phase-2 items in
+// the same model order, then the phase-3 items.  A workgroup takes the next
+// item from one atomic counter.  A phase-2 item waits until every phase-1
+// item of its model is finished (a per-model counter), a phase-3 item until
+// every phase-2 item is; each wait is only on items that running workgroups
+// took earlier, and items of an earlier phase never wait on a later one, so
+// every wait ends whatever the number of resident workgroups.  Each wait is
+// still bounded (kSpinLimit sleeps); running past the bound sets an error
+// word and the item proceeds, so the grid always drains.
+//
+// Per-model tuning (from the autotuner, or defaults): tiles per phase-1 item,
+// moves per phase-2 item, and the number of v rows each lane has in flight
+// (8, 16 or 32; a template argument of the tile code).
+#include "batch.h"
+#include "eval_dev.h"
+#include "topk_dev.h"
+
+namespace mps {
+
+constexpr int kBT = kNT;                 // threads per persistent workgroup
+constexpr int kSegCap = 1024;            // boundary keys refined in LDS
+constexpr int kSegLevels = 6;
+constexpr uint32_t kSpinLimit = 1u << 24;
+__constant__ int c_seg_shift[kSegLevels] = {52, 41, 30, 19, 8, 0};
+__constant__ int c_seg_bits[kSegLevels] = {12, 11, 11, 11, 11, 8};
+
+// LDS of the segmented top-k: histogram, part/res scratch, counters, the
+// selected keys and two candidate buffers.
+struct SegLds {
+    uint32_t *h;      // [kSegBins]
+    uint32_t *part;   // [4]
+    int32_t *res;     // [4]
+    int32_t *cnt;     // [4]: selected, candidates (two buffers), spare
+    uint64_t *sel;    // [MPS_MAX_BATCH_TOPK]
+    uint64_t *cand[2];// [kSegCap] each
+};
+
+__host__ __device__ inline size_t seg_lds_layout(char *base, SegLds *L) {
+    size_t off = 0;
+    auto put = [&](size_t bytes) {
+        const size_t o = off;
+        off = a16(off + bytes);
+        return o;
+    };
+    const size_t o_h = put(sizeof(uint32_t) * kSegBins);
+    const size_t o_p = put(sizeof(uint32_t) * 4);
+    const size_t o_r = put(sizeof(int32_t) * 4);
+    const size_t o_c = put(sizeof(int32_t) * 4);
+    const size_t o_s = put(sizeof(uint64_t) * MPS_MAX_BATCH_TOPK);
+    const size_t o_c0 = put(sizeof(uint64_t) * kSegCap);
+    const size_t o_c1 = put(sizeof(uint64_t) * kSegCap);
+    if (L) {
+        L->h = (uint32_t *)(base + o_h);
+        L->part = (uint32_t *)(base + o_p);
+        L->res = (int32_t *)(base + o_r);
+        L->cnt = (int32_t *)(base + o_c);
+        L->sel = (uint64_t *)(base + o_s);
+        L->cand[0] = (uint64_t *)(base + o_c0);
+        L->cand[1] = (uint64_t *)(base + o_c1);
+    }
+    return off;
+}
+
+size_t batch_lds_bytes(const DevModel &m) {
+    const size_t tile = tile_lds_layout(m, nullptr, nullptr);
+    const size_t moves = tile + sizeof(uint32_t) * kSegBins;
+    const size_t seg = seg_lds_layout(nullptr, nullptr);
+    return moves > seg ? moves : seg;
+}
+
+__global__ void k_batch_init(uint32_t *ctl, int64_t nwords) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+         i += (int64_t)gridDim.x * blockDim.x)
+        ctl[i] = 0u;
+}
+
+// Wait (thread 0 polls, the others meet it at the barrier) until *ctr >= need.
+__device__ void wait_count(const uint32_t *ctr, uint32_t need, uint32_t *err) {
+    if (threadIdx.x == 0) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins >= kSpinLimit) {
+                atomicOr(err, 1u);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Publish this workgroup's global writes, then count the item as finished.
+__device__ void signal_done(uint32_t *ctr) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- phase 1: per-block quantities of tiles [t0, t1) ------------------------
+template <int KCH>
+__device__ void batch_blocks(const DevModel &m, char *lds, int32_t t0, int32_t t1) {
+    TileLds L;
+    tile_lds_layout(m, lds, &L);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const TablePrefetch tp = issue_tables(m);
+    const TabView tv = commit_tables(m, L, tp);   // barrier inside
+    int32_t s0, s1;
+    wave_range(m, wave, s0, s1);
+    for (int32_t tile = t0; tile < t1; ++tile) {
+        const int64_t b = (int64_t)tile * 64 + lane;
+        const bool valid = b < m.N;
+        float x[KCH];
+        issue_rows(m, b, valid, s0, s1, x);
+        BlockInfo bi{};
+        if (valid && wave == 0) bi = load_block(m, b);
+        for (int32_t w = wave; w < m.W; w += kNW)
+            L.ore[w * 64 + lane] = valid ? gld(m.ore + (int64_t)w * m.N + b) : 0u;
+        L.cpart[wave * 64 + lane] = wave_dot(m, L.e, b, valid, s0, s1, x);
+        __syncthreads();
+        const float c = tile_c(L, lane, m.S);
+        if (wave == 0 && valid) {
+            auto ow = [&](int32_t w) { return L.ore[w * 64 + lane]; };
+            gst(m.blk_c + b, c);
+            gst(m.blk_rem + b, removal_term(m, tv, bi.pb, bi.ton32, ow));
+            gst(m.blk_info + b, (int32_t)(bi.pb | (bi.lo << 8) | (bi.hi << 16)));
+        }
+        __syncthreads();   // cpart and ore are rewritten by the next tile
+    }
+}
+
+// ---- phase 2: moves [i0, i1) of one model ------------------------------------
+__device__ void batch_moves(const DevModel &m, const BatchInst &I, char *lds, int64_t i0,
+                            int64_t i1, uint32_t *ghist, uint8_t req, uint8_t forbid) {
+    TileLds L;
+    tile_lds_layout(m, lds, &L);
+    uint32_t *h = (uint32_t *)L.end;
+    const int tid = threadIdx.x;
+    const TablePrefetch tp = issue_tables(m);
+    for (int j = tid; j < kSegBins; j += kBT) h[j] = 0u;
+    const TabView tv = commit_tables(m, L, tp);   // barrier inside
+    for (int64_t i = i0 + tid; i < i1; i += kBT) {
+        const MoveOut o = list_move(m, tv, L, gld(I.blk + i), (int32_t)gld(I.per + i));
+        gst(I.score + i, o.score);
+        gst(I.flags + i, o.flags);
+        uint64_t key;
+        if (key_from(o.score, o.flags, i, req, forbid, key))
+            atomicAdd(&h[(int)(key >> 52)], 1u);
+    }
+    __syncthreads();
+    for (int j = tid; j < kSegBins; j += kBT) {
+        const uint32_t c = h[j];
+        if (c) atomicAdd(&ghist[j], c);
+    }
+}
+
+// Bitonic sort of n (a power of two, <= MPS_MAX_BATCH_TOPK) keys in LDS,
+// descending.
+__device__ void sort_desc(uint64_t *s, int n) {
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < (n >> 1); i += kBT) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool desc = (lo & size) == 0;
+                const uint64_t a = s[lo], b = s[hi];
+                if ((a < b) == desc) {
+                    s[lo] = b;
+                    s[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---- phase 3: exact top k of one model --------------------------------------
+// Radix select on the 64-bit keys from the top digit down.  Level 0's
+// histogram was filled by the phase-2 items.  While the keys on the boundary
+// digit are too many for LDS, one pass over the model's moves appends the keys
+// above the boundary to the selection and counts the next digit of the keys on
+// it; once they fit, one pass collects them and the remaining levels run on
+// chip.  Keys are unique, so the boundary narrows to exactly the keys needed.
+__device__ void batch_topk(const BatchInst &I, char *lds, const uint32_t *ghist, int32_t k,
+                           uint8_t req, uint8_t forbid) {
+    SegLds L;
+    seg_lds_layout(lds, &L);
+    const int tid = threadIdx.x;
+    const int64_t n = I.n;
+    for (int j = tid; j < kSegBins; j += kBT) L.h[j] = ghist[j];
+    if (tid < 4) L.cnt[tid] = 0;
+    __syncthreads();
+    select_digit(L.h, kSegBins, k, L.part, L.res);   // barriers inside
+    const int32_t total = L.res[2];
+    int32_t n_sel_final;
+    if (total <= k) {
+        // every qualifying move is selected
+        for (int64_t i0 = 0; i0 < n; i0 += kBT) {
+            const int64_t i = i0 + tid;
+            uint64_t key = 0;
+            const bool q = i < n && key_from(gld(I.score + i), gld(I.flags + i), i, req, forbid, key);
+            wave_append(q, key, L.sel, &L.cnt[0]);
+        }
+        __syncthreads();
+        n_sel_final = L.cnt[0];
+    } else {
+        int level = 0;
+        int32_t need = k - L.res[1];
+        uint64_t pfx = (uint64_t)L.res[0];   // key >> shift[level] of the boundary
+        uint32_t n_eq = L.h[L.res[0]];
+        // global passes while the boundary keys do not fit on chip
+        while (n_eq > (uint32_t)kSegCap && level + 1 < kSegLevels) {
+            const int nb = 1 << c_seg_bits[level + 1];
+            __syncthreads();
+            for (int j = tid; j < nb; j += kBT) L.h[j] = 0u;
+            __syncthreads();
+            const int sh = c_seg_shift[level], sh1 = c_seg_shift[level + 1];
+            const int shp = level > 0 ? c_seg_shift[level - 1] : 64;
+            const uint64_t pfx_prev = pfx >> (shp - sh);   // unused at level 0
+            const uint64_t mask1 = (1ull << c_seg_bits[level + 1]) - 1ull;
+            for (int64_t i0 = 0; i0 < n; i0 += kBT) {
+                const int64_t i = i0 + tid;
+                uint64_t key = 0;
+                bool q = i < n && key_from(gld(I.score + i), gld(I.flags + i), i, req, forbid, key);
+                bool above = false;
+                if (q) {
+                    const uint64_t top = key >> sh;
+                    const bool in_prev = level == 0 || (key >> shp) == pfx_prev;
+                    above = in_prev && top > pfx;
+                    if (top == pfx) atomicAdd(&L.h[(int)((key >> sh1) & mask1)], 1u);
+                }
+                wave_append(above, key, L.sel, &L.cnt[0]);
+            }
+            __syncthreads();
+            select_digit(L.h, nb, need, L.part, L.res);
+            need -= L.res[1];
+            n_eq = L.h[L.res[0]];
+            pfx = (pfx << c_seg_bits[level + 1]) | (uint64_t)L.res[0];
+            ++level;
+        }
+        // collect the keys above the boundary (within the previous prefix)
+        // and the boundary keys themselves
+        {
+            const int sh = c_seg_shift[level];
+            const int shp = level > 0 ? c_seg_shift[level - 1] : 64;
+            const uint64_t pfx_prev = level > 0 ? pfx >> (shp - sh) : 0ull;
+            for (int64_t i0 = 0; i0 < n; i0 += kBT) {
+                const int64_t i = i0 + tid;
+                uint64_t key = 0;
+                const bool q = i < n && key_from(gld(I.score + i), gld(I.flags + i), i, req, forbid, key);
+                const uint64_t top = key >> sh;
+                const bool in_prev = level == 0 || (key >> shp) == pfx_prev;
+                wave_append(q && in_prev && top > pfx, key, L.sel, &L.cnt[0]);
+                wave_append(q && top == pfx, key, L.cand[0], &L.cnt[1]);
+            }
+            __syncthreads();
+        }
+        // refine the boundary on chip
+        int cb = 0;
+        while (need < L.cnt[1 + cb] && level + 1 < kSegLevels) {
+            const int nb = 1 << c_seg_bits[level + 1];
+            const int sh1 = c_seg_shift[level + 1];
+            const uint64_t mask1 = (1ull << c_seg_bits[level + 1]) - 1ull;
+            const int32_t nc = L.cnt[1 + cb];
+            const uint64_t *src = cb ? L.cand[1] : L.cand[0];
+            uint64_t *dst = cb ? L.cand[0] : L.cand[1];
+            for (int j = tid; j < nb; j += kBT) L.h[j] = 0u;
+            if (tid == 0) L.cnt[2 - cb] = 0;
+            __syncthreads();
+            for (int j = tid; j < nc; j += kBT)
+                atomicAdd(&L.h[(int)((src[j] >> sh1) & mask1)], 1u);
+            __syncthreads();
+            select_digit(L.h, nb, need, L.part, L.res);
+            const uint64_t dsel = (uint64_t)L.res[0];
+            need -= L.res[1];
+            for (int j0 = 0; j0 < nc; j0 += kBT) {
+                const int j = j0 + tid;
+                const uint64_t key = j < nc ? src[j] : 0ull;
+                const uint64_t d = (key >> sh1) & mask1;
+                wave_append(j < nc && d > dsel, key, L.sel, &L.cnt[0]);
+                wave_append(j < nc && d == dsel, key, dst, &L.cnt[2 - cb]);
+            }
+            __syncthreads();
+            cb = 1 - cb;
+            ++level;
+        }
+        // the remaining boundary keys are exactly the ones still needed
+        const int32_t nc = L.cnt[1 + cb];
+        const int32_t ns = L.cnt[0];
+        const uint64_t *last = cb ? L.cand[1] : L.cand[0];
+        for (int j = tid; j < nc; j += kBT) L.sel[ns + j] = last[j];
+        __syncthreads();
+        n_sel_final = ns + nc;
+    }
+    int P = 2;
+    while (P < n_sel_final) P <<= 1;
+    for (int j = n_sel_final + tid; j < P; j += kBT) L.sel[j] = 0ull;
+    __syncthreads();
+    sort_desc(L.sel, P);
+    for (int j = tid; j < k; j += kBT) {
+        if (j < n_sel_final) {
+            const uint64_t key = L.sel[j];
+            gst(I.top_idx + j, (int64_t)(0xffffffffu - (uint32_t)(key & 0xffffffffu)));
+            if (I.top_score) gst(I.top_score + j, unord_f32((uint32_t)(key >> 32)));
+        } else {
+            gst(I.top_idx + j, (int64_t)-1);
+            if (I.top_score) gst(I.top_score + j, -INFINITY);
+        }
+    }
+    if (tid == 0) gst(I.top_count, n_sel_final);
+}
+
+__global__ void __launch_bounds__(kBT) k_batch(const BatchInst *insts, const int2 *items,
+                                               int32_t n_items, int32_t n_inst, uint32_t *ctl,
+                                               int32_t k, uint8_t req, uint8_t forbid) {
+    extern __shared__ __align__(16) char lds[];
+    __shared__ int32_t s_item;
+    uint32_t *head = ctl, *err = ctl + 1;
+    uint32_t *done1 = ctl + 2, *done2 = done1 + n_inst;
+    uint32_t *ghist_all = done2 + n_inst;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(head, 1u);
+        __syncthreads();
+        const int32_t q = s_item;
+        __syncthreads();
+        if (q >= n_items) break;
+        const int2 it = items[q];
+        const BatchInst &I = insts[it.x];
+        const DevModel &m = I.m;
+        uint32_t *ghist = ghist_all + (size_t)it.x * kSegBins;
+        const int32_t j = it.y;
+        if (j < I.n1) {
+            const int32_t t0 = j * I.tiles_per_item;
+            const int32_t t1 = min(I.n_tiles, t0 + I.tiles_per_item);
+            if (I.rows <= 8)
+                batch_blocks<8>(m, lds, t0, t1);
+            else if (I.rows <= 16)
+                batch_blocks<16>(m, lds, t0, t1);
+            else
+                batch_blocks<32>(m, lds, t0, t1);
+            signal_done(&done1[it.x]);
+        } else if (j < I.n1 + I.n2) {
+            wait_count(&done1[it.x], (uint32_t)I.n1, err);
+            const int64_t i0 = (int64_t)(j - I.n1) * I.moves_per_item;
+            const int64_t i1 = min(I.n, i0 + I.moves_per_item);
+            batch_moves(m, I, lds, i0, i1, ghist, req, forbid);
+            signal_done(&done2[it.x]);
+        } else {
+            wait_count(&done2[it.x], (uint32_t)I.n2, err);
+            batch_topk(I, lds, ghist, k, req, forbid);
+            __syncthreads();   // LDS is reused by the next item
+        }
+    }
+}
+
+hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st) {
+    const int64_t nwords = batch_ctl_words(bl.n_inst);
+    int64_t g = (nwords + 255) / 256;
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(k_batch_init, dim3((unsigned)g), dim3(256), 0, st, bl.ctl, nwords);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (bl.n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch, dim3((unsigned)bl.grid), dim3(kBT), bl.lds_bytes, st, bl.insts,
+                       bl.items, bl.n_items, bl.n_inst, bl.ctl, bl.k, bl.req, bl.forbid);
+    return hipGetLastError();
+}
+
+hipError_t batch_occupancy(size_t lds_bytes, int *per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch, kBT, lds_bytes);
+}
+
+}  // namespace mps

@@ -1,0 +1,351 @@
+// eval_dev.h -- device helpers of move evaluation shared by the single-model
+// kernels (eval.hip) and the batched persistent kernel (batch.hip): the risk,
+// penalty and flag arithmetic of one move, the per-block loads, the LDS
+// staging of the penalty tables and the scenario-split dot product.
+#pragma once
+#include <float.h>
+
+#include "internal.h"
+
+namespace mps {
+
+constexpr int kListCap = 256;   // partial-list entries staged in LDS per kind
+constexpr int kNW = 8;          // waves per 64-block tile
+constexpr int kNT = 64 * kNW;   // threads per tile
+constexpr int kCH = 32;         // v rows in flight per lane
+
+struct MoveOut {
+    float score, dr, dpp, dpm;
+    uint8_t flags;
+};
+
+// View of the penalty tables (LDS copies; long lists stay in HBM).
+struct TabView {
+    const uint32_t *full_add, *full_rem;   // [T][W]
+    const int32_t *rng;                    // [4][T] list ranges
+    const AddEntry *add_l, *add_g;         // list entries: LDS copy / in HBM
+    const RemEntry *rem_l, *rem_g;
+    bool small;                            // the lists fit their LDS copies
+};
+
+// Risk, penalty and flag arithmetic of one move, given the block quantities.
+// ore_word(w) returns ore word w of block b.
+template <class OreWord>
+__device__ __forceinline__ MoveOut score_move(const DevModel &m, const TabView &tv,
+                                              const double *d64, const double *Ms, int32_t t,
+                                              int32_t pb, int32_t lo, int32_t hi, float c,
+                                              float remv, float ton32, double ton64, float mb,
+                                              float Vb, float var32, float sig32, float lam,
+                                              float pps, OreWord ore_word) {
+    const int32_t T = m.T;
+    MoveOut o;
+    const bool noop = (t == pb);
+    const float dd = (float)(d64[t] - d64[pb]);
+    const float dvar = fmaf(2.0f * dd, c, dd * dd * Vb);
+    const float vp = fmaxf(var32 + dvar, 0.0f);
+    const float den = sqrtf(vp) + sig32;
+    const float dsig = den > 0.0f ? dvar / den : 0.0f;
+    const float dr = fmaf(dd, mb, -lam * dsig);
+
+    float addv = 0.0f;
+    bool viol = false;
+    if (t < T && !noop) {
+        int32_t cnt = 0;
+        const uint32_t *fa = tv.full_add + (int64_t)t * m.W;
+        for (int32_t w = 0; w < m.W; ++w) cnt += __popc(ore_word(w) & fa[w]);
+        addv = (float)cnt * ton32;
+        viol = cnt != 0;
+        const int32_t j0 = tv.rng[t], j1 = tv.rng[T + t];
+        auto entry = [&](const AddEntry &e) {
+            if ((ore_word(e.s >> 5) >> (e.s & 31)) & 1u) {
+                addv += fmaxf(ton32 - e.d, 0.0f);
+                if (ton64 >= e.tau) viol = true;
+            }
+        };
+        // one loop per memory: LDS copy, or the lists in HBM
+        if (tv.small)
+            for (int32_t j = j0; j < j1; ++j) entry(tv.add_l[j]);
+        else
+            for (int32_t j = j0; j < j1; ++j) entry(gld(tv.add_g + j));
+    }
+    double am = 0.0;
+    bool mine_ok = true;
+    if (!noop) {
+        if (t < T) {
+            const double Mt = Ms[t];
+            am += hinge64(Mt + ton64, m.mcap) - hinge64(Mt, m.mcap);
+            mine_ok = Mt + ton64 <= m.mcap;
+        }
+        if (pb < T) {
+            const double Mp = Ms[pb];
+            am += hinge64(Mp - ton64, m.mcap) - hinge64(Mp, m.mcap);
+        }
+    }
+    const float dpp = noop ? 0.0f : pps * (addv - remv);
+    const float dpm = (float)(m.pen_mine * am);
+    uint8_t f = 0;
+    if (lo <= t && t <= hi) f |= MPS_PREC_OK;
+    if (noop || t == T || mine_ok) f |= MPS_MINE_OK;
+    if (noop || t == T || !viol) f |= MPS_PROC_OK;
+    if (noop) f |= MPS_NOOP;
+    o.flags = f;
+    o.dr = noop ? 0.0f : dr;
+    o.dpp = dpp;
+    o.dpm = noop ? 0.0f : dpm;
+    o.score = noop ? 0.0f : (dr - dpp) - dpm;
+    return o;
+}
+
+// Removal term of block b from its current period pb:
+// sum_s ore[s][b] * clamp(O[pb][s] - cap, 0, ton_b)  (0 when pb = T).
+template <class OreWord>
+__device__ __forceinline__ float removal_term(const DevModel &m, const TabView &tv, int32_t pb,
+                                              float ton32, OreWord ore_word) {
+    const int32_t T = m.T;
+    if (pb >= T) return 0.0f;
+    int32_t cnt = 0;
+    const uint32_t *fr = tv.full_rem + (int64_t)pb * m.W;
+    for (int32_t w = 0; w < m.W; ++w) cnt += __popc(ore_word(w) & fr[w]);
+    float r = (float)cnt * ton32;
+    const int32_t j0 = tv.rng[2 * T + pb], j1 = tv.rng[3 * T + pb];
+    auto entry = [&](const RemEntry &e) {
+        if ((ore_word(e.s >> 5) >> (e.s & 31)) & 1u) r += fminf(e.a, ton32);
+    };
+    if (tv.small)
+        for (int32_t j = j0; j < j1; ++j) entry(tv.rem_l[j]);
+    else
+        for (int32_t j = j0; j < j1; ++j) entry(gld(tv.rem_g + j));
+    return r;
+}
+
+// Per-lane block quantities used by every destination.
+struct BlockInfo {
+    int32_t pb, lo, hi;
+    float ton32, mb, Vb;
+    double ton64;
+};
+
+// Loads of block b's data; the precedence window (lo = max p over
+// predecessors or 0, hi = min p over successors or T) comes from ten loads
+// issued unconditionally (invalid neighbours read b itself and are masked).
+__device__ __forceinline__ BlockInfo load_block(const DevModel &m, int64_t b) {
+    BlockInfo bi;
+    int32_t x, y, z;
+    grid_coords(m, (int32_t)b, x, y, z);
+    const int64_t nxy = (int64_t)m.nx * m.ny;
+    const bool up = z > 0, dn = z + 1 < m.nz;
+    const bool in[5] = {true, x > 0, x + 1 < m.nx, y > 0, y + 1 < m.ny};
+    const int64_t off[5] = {0, -1, 1, -(int64_t)m.nx, (int64_t)m.nx};
+    int32_t pu[5], pd[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        pu[k] = gld(m.p + ((up && in[k]) ? b - nxy + off[k] : b));
+        pd[k] = gld(m.p + ((dn && in[k]) ? b + nxy + off[k] : b));
+    }
+    bi.pb = gld(m.p + b);
+    bi.ton32 = gld(m.ton32 + b);
+    bi.ton64 = gld(m.ton64 + b);
+    bi.mb = gld(m.mb32 + b);
+    bi.Vb = gld(m.Vb32 + b);
+    bi.lo = 0;
+    bi.hi = m.T;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        if (up && in[k]) bi.lo = max(bi.lo, pu[k]);
+        if (dn && in[k]) bi.hi = min(bi.hi, pd[k]);
+    }
+    return bi;
+}
+
+struct TileLds {
+    double *d64;      // [T+1]
+    double *Ms;       // [T]
+    float *cpart;     // [kNW][64]
+    float *e;         // [S] scenario weights N_s - mu
+    uint32_t *ore;    // [W][64]
+    uint32_t *fa;     // [T][W]
+    uint32_t *fr;     // [T][W]
+    int32_t *rng;     // [4][T]
+    AddEntry *al;     // [kListCap]
+    RemEntry *rl;     // [kListCap]
+    char *end;
+};
+
+__host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ inline size_t tile_lds_layout(const DevModel &m, char *base, TileLds *L) {
+    size_t off = 0;
+    auto put = [&](size_t bytes) {
+        const size_t o = off;
+        off = a16(off + bytes);
+        return o;
+    };
+    const size_t o_d = put(sizeof(double) * (m.T + 1));
+    const size_t o_M = put(sizeof(double) * m.T);
+    const size_t o_c = put(sizeof(float) * 64 * kNW);
+    const size_t o_e = put(sizeof(float) * m.S);
+    const size_t o_o = put(sizeof(uint32_t) * 64 * m.W);
+    const size_t o_fa = put(sizeof(uint32_t) * m.T * m.W);
+    const size_t o_fr = put(sizeof(uint32_t) * m.T * m.W);
+    const size_t o_rg = put(sizeof(int32_t) * 4 * m.T);
+    const size_t o_al = put(sizeof(AddEntry) * kListCap);
+    const size_t o_rl = put(sizeof(RemEntry) * kListCap);
+    if (L) {
+        L->d64 = (double *)(base + o_d);
+        L->Ms = (double *)(base + o_M);
+        L->cpart = (float *)(base + o_c);
+        L->e = (float *)(base + o_e);
+        L->ore = (uint32_t *)(base + o_o);
+        L->fa = (uint32_t *)(base + o_fa);
+        L->fr = (uint32_t *)(base + o_fr);
+        L->rng = (int32_t *)(base + o_rg);
+        L->al = (AddEntry *)(base + o_al);
+        L->rl = (RemEntry *)(base + o_rl);
+        L->end = base + off;
+    }
+    return off;
+}
+
+// Table staging in two halves: issue (loads into registers) and commit (LDS
+// stores), so that the loads travel together with the tile's v stream.
+struct TablePrefetch {
+    double d, M;
+    uint32_t fa, fr;
+    int32_t rg;
+    float e;
+    AddEntry ae;
+    RemEntry re;
+};
+
+__device__ __forceinline__ TablePrefetch issue_tables(const DevModel &m) {
+    const int tid = threadIdx.x;
+    const int32_t T = m.T, TW = m.T * m.W;
+    TablePrefetch f;
+    f.d = tid <= T ? gld(m.d64 + tid) : 0.0;
+    f.M = tid < T ? gld(m.M + tid) : 0.0;
+    f.fa = tid < TW ? gld(m.tab.full_add + tid) : 0u;
+    f.fr = tid < TW ? gld(m.tab.full_rem + tid) : 0u;
+    f.rg = tid < 4 * T ? gld(m.tab.rng + tid) : 0;
+    f.e = tid < m.S ? gld(m.e32 + tid) : 0.0f;
+    f.ae = gld(m.tab.add_packed + min(tid, kListCap - 1));
+    f.re = gld(m.tab.rem_packed + min(tid, kListCap - 1));
+    return f;
+}
+
+// Commit the prefetched tables to LDS (plus any remainder of large tables),
+// then barrier.  Lists longer than kListCap in total are read in place.
+__device__ __forceinline__ TabView commit_tables(const DevModel &m, const TileLds &L,
+                                                 const TablePrefetch &f) {
+    const int tid = threadIdx.x;
+    const int32_t T = m.T, TW = m.T * m.W;
+    if (tid <= T) L.d64[tid] = f.d;
+    if (tid < T) L.Ms[tid] = f.M;
+    if (tid < TW) {
+        L.fa[tid] = f.fa;
+        L.fr[tid] = f.fr;
+    }
+    if (tid < 4 * T) L.rng[tid] = f.rg;
+    if (tid < m.S) L.e[tid] = f.e;
+    for (int i = tid + kNT; i < TW; i += kNT) {   // tables beyond one word per thread
+        L.fa[i] = gld(m.tab.full_add + i);
+        L.fr[i] = gld(m.tab.full_rem + i);
+    }
+    for (int i = tid + kNT; i < m.S; i += kNT) L.e[i] = gld(m.e32 + i);
+    if (tid < kListCap) {
+        L.al[tid] = f.ae;
+        L.rl[tid] = f.re;
+    }
+    __syncthreads();
+    TabView tv;
+    tv.full_add = L.fa;
+    tv.full_rem = L.fr;
+    tv.rng = L.rng;
+    const bool small = L.rng[2 * T - 1] <= kListCap && L.rng[4 * T - 1] <= kListCap;
+    tv.small = small;
+    tv.add_l = L.al;
+    tv.add_g = m.tab.add_packed;
+    tv.rem_l = L.rl;
+    tv.rem_g = m.tab.rem_packed;
+    return tv;
+}
+
+// This wave's share [s0, s1) of the scenarios (wave-uniform).
+__device__ __forceinline__ void wave_range(const DevModel &m, int wave, int32_t &s0,
+                                           int32_t &s1) {
+    const int32_t Sw = (m.S + kNW - 1) / kNW;
+    s0 = wave * Sw;
+    s1 = min(m.S, s0 + Sw);
+}
+
+// Issue the loads of one chunk of kCH rows of v (all before any FMA).
+template <int KCH>
+__device__ __forceinline__ void issue_rows(const DevModel &m, int64_t b, bool valid, int32_t s,
+                                           int32_t s1, float (&x)[KCH]) {
+    const float *vp = m.v + b;
+#pragma unroll
+    for (int k = 0; k < KCH; ++k) {
+        x[k] = 0.0f;
+        if (valid && s + k < s1) x[k] = gld_nt(vp + (int64_t)(s + k) * m.N);
+    }
+}
+
+template <int KCH>
+__device__ __forceinline__ float fma_rows(const float *e, int32_t s, int32_t s1,
+                                          const float (&x)[KCH], float acc) {
+#pragma unroll
+    for (int k = 0; k < KCH; ++k)
+        if (s + k < s1) acc = fmaf(e[s + k], x[k], acc);
+    return acc;
+}
+
+// Dot product of this wave's share: the first KCH rows were issued by the
+// caller before the table round trip; rows beyond them (S > kNW*KCH) follow
+// eight at a time.
+template <int KCH>
+__device__ __forceinline__ float wave_dot(const DevModel &m, const float *e, int64_t b,
+                                          bool valid, int32_t s0, int32_t s1, float (&x)[KCH]) {
+    float acc = fma_rows(e, s0, s1, x, 0.0f);
+    if (valid) {
+        const float *vp = m.v + b;
+        for (int32_t s = s0 + KCH; s < s1; s += 8) {
+            float y[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                y[k] = s + k < s1 ? gld_nt(vp + (int64_t)(s + k) * m.N) : 0.0f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (s + k < s1) acc = fmaf(e[s + k], y[k], acc);
+        }
+    }
+    return acc;
+}
+
+// c_b from the per-wave partials (fixed order).
+__device__ __forceinline__ float tile_c(const TileLds &L, int lane, int32_t S) {
+    float c = L.cpart[lane];
+#pragma unroll
+    for (int w = 1; w < kNW; ++w) c += L.cpart[w * 64 + lane];
+    return c / (float)S;
+}
+
+// One listed move (b, t) from the per-block quantities the list pass wrote
+// (blk_c, blk_rem, blk_info); a move out of range is BAD with score -FLT_MAX.
+__device__ __forceinline__ MoveOut list_move(const DevModel &m, const TabView &tv,
+                                             const TileLds &L, int32_t b, int32_t t) {
+    if (b < 0 || (int64_t)b >= m.N || t < 0 || t > m.T) {
+        MoveOut o;
+        o.score = -FLT_MAX;
+        o.flags = MPS_BAD;
+        o.dr = o.dpp = o.dpm = 0.0f;
+        return o;
+    }
+    const int32_t info = gld(m.blk_info + b);
+    const int32_t pb = info & 0xff, lo = (info >> 8) & 0xff, hi = (info >> 16) & 0xff;
+    auto ow = [&](int32_t w) { return gld(m.ore + (int64_t)w * m.N + b); };
+    return score_move(m, tv, L.d64, L.Ms, t, pb, lo, hi, gld(m.blk_c + b), gld(m.blk_rem + b),
+                      gld(m.ton32 + b), gld(m.ton64 + b), gld(m.mb32 + b), gld(m.Vb32 + b),
+                      gld(&m.sc->var32), gld(&m.sc->sigma32),
+                      (float)m.lambda, (float)(m.pen_proc / m.S), ow);
+}
+
+}  // namespace mps

@@ -118,6 +118,35 @@ hipError_t launch_rank(const DevModel &m, const float *grad, int32_t k, int32_t 
                        int8_t *per, float *gain_out, int32_t *count, void *ws, hipStream_t st);
 hipError_t launch_integer_x(const DevModel &m, float *x, hipStream_t st);
 
+// Global-memory access through an explicitly global pointer.  Pointers held
+// in device-memory descriptors (not kernel arguments) are otherwise generic,
+// and generic (flat) accesses also count against the LDS wait counter.
+template <class T>
+__device__ __forceinline__ T gld(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ T gld_nt(const T *p) {
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) T *)p);
+}
+template <class T>
+__device__ __forceinline__ void gst(T *p, const T &v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+__device__ __forceinline__ AddEntry gld(const AddEntry *p) {
+    AddEntry e;
+    e.tau = gld(&p->tau);
+    e.d = gld(&p->d);
+    e.s = gld(&p->s);
+    return e;
+}
+__device__ __forceinline__ RemEntry gld(const RemEntry *p) {
+    RemEntry e;
+    e.a = gld(&p->a);
+    e.s = gld(&p->s);
+    return e;
+}
+
 // Precedence neighbours under the 1-5 stencil; shared by the kernels.
 __device__ __forceinline__ void grid_coords(const DevModel &m, int32_t b,
                                             int32_t &x, int32_t &y, int32_t &z) {

@@ -207,7 +207,9 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
     double *dl = (double *)(lds + Lo.d);
     int32_t *hkey = (int32_t *)(lds + Lo.hkey);
     int8_t *hval = (int8_t *)(lds + Lo.hval);
-    char *bufp[2] = {lds + Lo.buf[0], lds + Lo.buf[1]};
+    // the two batch buffers; selected by offset so that every access stays
+    // an LDS access
+    const size_t boff0 = Lo.buf[0], boff1 = Lo.buf[1];
     // per wave: mu, var, sigma after its candidate's move; then mu, var,
     // sigma of the current state; then the wave's current period of the
     // block and one accept byte per wave
@@ -236,7 +238,7 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
         }
     };
     auto commit = [&](int buf, const float4 (&pf)[kPf]) {
-        float4 *dst = (float4 *)bufp[buf];
+        float4 *dst = (float4 *)(lds + (buf ? boff1 : boff0));
         const size_t cap = (size_t)B * rb;
 #pragma unroll
         for (int k = 0; k < kPf; ++k) {
@@ -279,7 +281,7 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
     for (int32_t c0 = 0; c0 < n; c0 += B) {
         const int32_t c1 = min(n, c0 + B);
         if (c1 < n) issue(c1, pf);   // next batch travels while this one is walked
-        const char *bb = bufp[buf];
+        const char *bb = lds + (buf ? boff1 : boff0);
         int32_t pos = c0;
         while (pos < c1) {
             const int32_t ne = min(kWaves, c1 - pos);
@@ -370,7 +372,7 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
             __syncthreads();
             // ---- the first accepted candidate of the round, if any: one
             // byte per wave, read as one 64-bit word
-            const uint64_t am = *(const volatile uint64_t *)acc & 0x0101010101010101ull;
+            const uint64_t am = *(const uint64_t *)acc & 0x0101010101010101ull;
             const int32_t r = am ? (__builtin_ctzll(am) >> 3) : ne;
             if (r < ne) {
                 const char *rp = bb + (size_t)(pos + r - c0) * rb;

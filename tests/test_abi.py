@@ -87,3 +87,30 @@ def test_topk_ws_bytes_grows_with_n_and_k():
     from paper_2511_18296_amd import binding
     f = binding.lib.mps_topk_ws_bytes
     assert f(1000, 10) < f(100000, 10) and f(1000, 10) < f(1000, 4000)
+
+
+def test_batch_argument_checks():
+    """Batch entry points reject NULL handles and out-of-range k / counts on
+    the host."""
+    from paper_2511_18296_amd import binding
+    L = binding.lib
+    out = C.c_void_p()
+    items = (binding.BatchItem * 1)()
+    models = (C.c_void_p * 1)(None)
+    assert L.mps_batch_create(None, items, 1, 4, 1, 24, C.byref(out)) == 1
+    assert L.mps_batch_create(models, items, 1, 4, 1, 24, None) == 1
+    assert L.mps_batch_create(models, items, 0, 4, 1, 24, C.byref(out)) == 1
+    assert L.mps_batch_create(models, items, 1, 0, 1, 24, C.byref(out)) == 1
+    assert L.mps_batch_create(models, items, 1, 1025, 1, 24, C.byref(out)) == 1
+    assert L.mps_batch_create(models, items, 1, 4, 1, 24, C.byref(out)) == 1   # NULL model
+    assert out.value is None
+    t = binding.Tuning(1, 512, 8, 0)
+    assert L.mps_batch_destroy(None) == 1
+    assert L.mps_batch_set_tuning(None, -1, C.byref(t)) == 1
+    assert L.mps_batch_get_tuning(None, 0, C.byref(t)) == 1
+    assert L.mps_batch_set_workgroups(None, 0) == 1
+    assert L.mps_batch_run(None, None) == 1
+    assert L.mps_batch_graph_launch(None, None) == 1
+    assert L.mps_batch_autotune(None, 3, None, None) == 1
+    e = C.c_int32()
+    assert L.mps_batch_error(None, C.byref(e), None) == 1
