@@ -270,13 +270,12 @@ mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_par
 /* ---- batched evaluation ---------------------------------------------------
  * Many models (for instance, one schedule per individual of the population
  * the metaheuristic of Alg. 2 keeps), each with its own list of candidate
- * moves of any length, are evaluated in ONE persistent kernel launch that
- * ends with every model's exact top k.  The launch is a queue of work items:
- * per-block passes over each model's block values, then chunks of each
- * model's moves, then each model's top-k selection (largest model first);
- * workgroups that stay resident for the whole launch take items from one
- * atomic counter.  Results equal those of mps_eval_moves on each model's
- * list followed by mps_topk with the same k, require and forbid.
+ * moves of any length, are evaluated by persistent workgroups and end with
+ * every model's exact top k.  Three persistent launches each take work
+ * items from an atomic counter, largest model first: per-block passes over
+ * each model's block values, then chunks of each model's moves, then one
+ * top-k selection per model.  Results equal those of mps_eval_moves on each
+ * model's list followed by mps_topk with the same k, require and forbid.
  *
  * Tuning: how the work of one model is cut into items, set per model (the
  * autotuner sets it per class of models with the same S range). */
@@ -324,7 +323,8 @@ mps_status mps_batch_get_tuning(const mps_batch *b, int32_t i, mps_tuning *t);
 mps_status mps_batch_set_workgroups(mps_batch *b, int32_t n);
 
 /* Enqueue the batch on `stream`: one small clearing kernel (no memset) and
- * the persistent kernel.  Capturable.  Calls on one batch must not overlap. */
+ * the three persistent launches.  Capturable.  Calls on one batch must not
+ * overlap. */
 mps_status mps_batch_run(mps_batch *b, void *stream);
 
 /* The same work replayed as a HIP graph: the first call captures
@@ -341,10 +341,6 @@ mps_status mps_batch_graph_launch(mps_batch *b, void *stream);
  * hold the results of its last timed run.  Synchronises; not capturable.
  * *best_us (may be NULL) receives the median time of the chosen tuning. */
 mps_status mps_batch_autotune(mps_batch *b, int32_t reps, double *best_us, void *stream);
-
-/* Error word of the last run (synchronises `stream`): 0, or 1 when a wait of
- * the persistent kernel on a dependency ran past its bound. */
-mps_status mps_batch_error(mps_batch *b, int32_t *err, void *stream);
 
 #ifdef __cplusplus
 }

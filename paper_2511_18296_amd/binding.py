@@ -110,7 +110,6 @@ def _load():
         "mps_batch_run": ([vp, vp], st),
         "mps_batch_graph_launch": ([vp, vp], st),
         "mps_batch_autotune": ([vp, i32, vp, vp], st),
-        "mps_batch_error": ([vp, vp, vp], st),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -130,7 +129,7 @@ EXPORTS = ("mps_last_error", "mps_version", "mps_device_count", "mps_build_model
            "mps_rank_ws_bytes", "mps_rank_moves", "mps_search", "mps_state_bytes",
            "mps_state_save", "mps_state_restore", "mps_batch_create", "mps_batch_destroy",
            "mps_batch_set_tuning", "mps_batch_get_tuning", "mps_batch_set_workgroups",
-           "mps_batch_run", "mps_batch_graph_launch", "mps_batch_autotune", "mps_batch_error")
+           "mps_batch_run", "mps_batch_graph_launch", "mps_batch_autotune")
 
 
 def check(status: int):
@@ -467,9 +466,3 @@ class Batch:
         us = C.c_double(0.0)
         check(lib.mps_batch_autotune(self.h, int(reps), C.byref(us), _stream(stream)))
         return us.value
-
-    def error(self, stream=None) -> int:
-        e = C.c_int32(0)
-        check(lib.mps_batch_error(self.h, C.byref(e), _stream(stream)))
-        return e.value
-

@@ -731,10 +731,11 @@ struct mps_batch {
     std::vector<mps_tuning> tune;
     std::vector<int32_t> order;   // models by decreasing block-value bytes
     BatchInst *d_insts = nullptr;
-    int2 *d_items = nullptr;
+    int2 *d_items1 = nullptr, *d_items2 = nullptr;
+    int32_t *d_order = nullptr;
     uint32_t *d_ctl = nullptr;
-    int64_t max_items = 0;
-    int32_t n_items = 0;
+    int64_t max_items1 = 0, max_items2 = 0;
+    int32_t n_items1 = 0, n_items2 = 0;
     size_t lds = 0;
     int per_cu = 1, cus = 1, workgroups = 0;
     hipStream_t cap = nullptr;
@@ -747,23 +748,27 @@ struct mps_batch {
         exec = nullptr;
         graph = nullptr;
     }
-    int grid() const {
+    int grid(int32_t items) const {
         const int full = per_cu * cus;
         int g = workgroups > 0 ? std::min(workgroups, full) : full;
-        if ((int64_t)g > n_items) g = (int)n_items;
+        if ((int64_t)g > items) g = (int)items;
         return g > 0 ? g : 1;
     }
     BatchLaunch launch() const {
         BatchLaunch bl;
         bl.insts = d_insts;
-        bl.items = d_items;
-        bl.n_items = n_items;
+        bl.items1 = d_items1;
+        bl.items2 = d_items2;
+        bl.order = d_order;
+        bl.n_items1 = n_items1;
+        bl.n_items2 = n_items2;
         bl.n_inst = n;
         bl.ctl = d_ctl;
         bl.k = k;
         bl.req = req;
         bl.forbid = forbid;
-        bl.grid = grid();
+        bl.grid1 = grid(n_items1);
+        bl.grid2 = grid(n_items2);
         bl.lds_bytes = lds;
         return bl;
     }
@@ -789,20 +794,24 @@ struct mps_batch {
             I.n2 = (int32_t)((it.n + I.moves_per_item - 1) / I.moves_per_item);
             I.rows = tune[i].rows;
         }
-        std::vector<int2> q;
-        q.reserve((size_t)max_items);
+        std::vector<int2> q1, q2;
         for (int32_t i : order)
-            for (int32_t j = 0; j < hi[i].n1; ++j) q.push_back(make_int2(i, j));
+            for (int32_t j = 0; j < hi[i].n1; ++j) q1.push_back(make_int2(i, j));
         for (int32_t i : order)
-            for (int32_t j = 0; j < hi[i].n2; ++j) q.push_back(make_int2(i, hi[i].n1 + j));
-        for (int32_t i : order) q.push_back(make_int2(i, hi[i].n1 + hi[i].n2));
-        if ((int64_t)q.size() > max_items) return fail(MPS_E_INTERNAL, "work queue overflow");
+            for (int32_t j = 0; j < hi[i].n2; ++j) q2.push_back(make_int2(i, j));
+        if ((int64_t)q1.size() > max_items1 || (int64_t)q2.size() > max_items2)
+            return fail(MPS_E_INTERNAL, "work queue overflow");
         DeviceGuard g(device);
         hipError_t e = hipMemcpy(d_insts, hi.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess && !q1.empty())
+            e = hipMemcpy(d_items1, q1.data(), sizeof(int2) * q1.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !q2.empty())
+            e = hipMemcpy(d_items2, q2.data(), sizeof(int2) * q2.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMemcpy(d_items, q.data(), sizeof(int2) * q.size(), hipMemcpyHostToDevice);
+            e = hipMemcpy(d_order, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
         if (e != hipSuccess) return dev_fail(e, "batch descriptors");
-        n_items = (int32_t)q.size();
+        n_items1 = (int32_t)q1.size();
+        n_items2 = (int32_t)q2.size();
         drop_graph();
         return MPS_OK;
     }
@@ -811,7 +820,9 @@ struct mps_batch {
         drop_graph();
         if (cap) hipStreamDestroy(cap);
         hipFree(d_insts);
-        hipFree(d_items);
+        hipFree(d_items1);
+        hipFree(d_items2);
+        hipFree(d_order);
         hipFree(d_ctl);
     }
 };
@@ -829,7 +840,7 @@ mps_status mps_batch_create(mps_model *const *models, const mps_batch_item *item
     if (k < 1 || k > MPS_MAX_BATCH_TOPK)
         return fail(MPS_E_INVALID_ARG, "k must be in 1..%d (got %d)", MPS_MAX_BATCH_TOPK, k);
     size_t lds = 0;
-    int64_t max_items = 0;
+    int64_t max_items1 = 0, max_items2 = 0;
     for (int32_t i = 0; i < n_models; ++i) {
         const mps_model *m = models[i];
         const mps_batch_item &it = items[i];
@@ -843,12 +854,14 @@ mps_status mps_batch_create(mps_model *const *models, const mps_batch_item *item
         if (!it.top_idx || !it.top_count)
             return fail(MPS_E_INVALID_ARG, "item %d: top_idx and top_count are required", i);
         lds = std::max(lds, batch_lds_bytes(m->d));
-        max_items += (m->d.N + 63) / 64 + (it.n + 511) / 512 + 1;
+        max_items1 += (m->d.N + 63) / 64;
+        max_items2 += (it.n + 511) / 512;
     }
     if (lds > (size_t)models[0]->max_lds)
         return fail(MPS_E_INVALID_ARG, "batch needs %zu bytes of LDS, device allows %d", lds,
                     models[0]->max_lds);
-    if (max_items >= ((int64_t)1 << 31)) return fail(MPS_E_INVALID_ARG, "batch too large");
+    if (max_items1 >= ((int64_t)1 << 31) || max_items2 >= ((int64_t)1 << 31))
+        return fail(MPS_E_INVALID_ARG, "batch too large");
     mps_batch *b = new mps_batch;
     b->device = models[0]->device;
     b->n = n_models;
@@ -858,7 +871,8 @@ mps_status mps_batch_create(mps_model *const *models, const mps_batch_item *item
     b->models.assign(models, models + n_models);
     b->items.assign(items, items + n_models);
     b->lds = lds;
-    b->max_items = max_items;
+    b->max_items1 = max_items1;
+    b->max_items2 = max_items2;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         for (int32_t i = 0; i < n_models; ++i) {
@@ -877,7 +891,11 @@ mps_status mps_batch_create(mps_model *const *models, const mps_batch_item *item
     if (e == hipSuccess) e = batch_occupancy(lds, &b->per_cu);
     if (e == hipSuccess && b->per_cu < 1) e = hipErrorInvalidConfiguration;
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_insts, sizeof(BatchInst) * n_models);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_items, sizeof(int2) * (size_t)max_items);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->d_items1, sizeof(int2) * (size_t)std::max<int64_t>(max_items1, 1));
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->d_items2, sizeof(int2) * (size_t)std::max<int64_t>(max_items2, 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_order, sizeof(int32_t) * n_models);
     if (e == hipSuccess)
         e = hipMalloc((void **)&b->d_ctl, sizeof(uint32_t) * (size_t)batch_ctl_words(n_models));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
@@ -966,19 +984,6 @@ mps_status mps_batch_graph_launch(mps_batch *b, void *stream) {
     }
     hipError_t e = hipGraphLaunch(b->exec, hs);
     return e == hipSuccess ? MPS_OK : dev_fail(e, "launch batch graph");
-}
-
-mps_status mps_batch_error(mps_batch *b, int32_t *err, void *stream) {
-    if (!b || !err) return fail(MPS_E_INVALID_ARG, "batch and err are required");
-    hipStream_t hs = (hipStream_t)stream;
-    if (capturing(hs)) return fail(MPS_E_NOT_CAPTURABLE, "mps_batch_error during capture");
-    DeviceGuard g(b->device);
-    uint32_t w = 0;
-    hipError_t e = hipMemcpyAsync(&w, b->d_ctl + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, hs);
-    if (e == hipSuccess) e = hipStreamSynchronize(hs);
-    if (e != hipSuccess) return dev_fail(e, "batch error word");
-    *err = (int32_t)w;
-    return MPS_OK;
 }
 
 mps_status mps_batch_autotune(mps_batch *b, int32_t reps, double *best_us, void *stream) {

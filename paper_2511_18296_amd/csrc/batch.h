@@ -20,25 +20,27 @@ struct BatchInst {
     float *top_score;
     int32_t *top_count;
     int32_t n_tiles;          // 64-block tiles of the model
-    int32_t tiles_per_item;   // tiles per phase-1 item
-    int32_t n1, n2;           // phase-1 and phase-2 items
-    int32_t moves_per_item;   // moves per phase-2 item
+    int32_t tiles_per_item;   // tiles per block item
+    int32_t n1, n2;           // block items and move items
+    int32_t moves_per_item;   // moves per move item
     int32_t rows;             // v rows in flight per lane (8, 16, 32)
 };
 
 struct BatchLaunch {
     const BatchInst *insts;
-    const int2 *items;        // (model, item) in queue order
-    int32_t n_items, n_inst;
-    uint32_t *ctl;            // head, error, done1[n], done2[n], hist[n][kSegBins]
+    const int2 *items1;       // block items (model, item) in queue order
+    const int2 *items2;       // move items
+    const int32_t *order;     // models, largest first
+    int32_t n_items1, n_items2, n_inst;
+    uint32_t *ctl;            // head1, head2, hist[n][kSegBins]
     int32_t k;
     uint8_t req, forbid;
-    int grid;
+    int grid1, grid2;
     size_t lds_bytes;
 };
 
 inline int64_t batch_ctl_words(int32_t n_inst) {
-    return 2 + 2 * (int64_t)n_inst + (int64_t)kSegBins * n_inst;
+    return 2 + (int64_t)kSegBins * n_inst;
 }
 
 size_t batch_lds_bytes(const DevModel &m);

