@@ -322,19 +322,39 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
                     const double dd = dl[t] - dl[pb];
                     double cp = 0.0, pen = 0.0;
                     bool viol = false;
-                    for (int32_t s = lane; s < S; s += 64) {
-                        const double vs = (double)vb[s];
-                        cp += (Ns[s] - mu) * vs;
-                        if ((ob[s >> 5] >> (s & 31)) & 1u) {
-                            if (t < T) {
-                                const double o = O[(int64_t)t * S + s];
-                                pen += hinge64(o + ton, m.pcap) - hinge64(o, m.pcap);
-                                if (o + ton > m.pcap) viol = true;
-                            }
-                            if (pb < T) {
-                                const double o = O[(int64_t)pb * S + s];
-                                pen += hinge64(o - ton, m.pcap) - hinge64(o, m.pcap);
-                            }
+                    // rows of the two touched periods (a valid row when the
+                    // period is "never"; its terms are then masked off)
+                    const bool tin = t < T, pin = pb < T;
+                    const double *Ot = O + (int64_t)(tin ? t : 0) * S;
+                    const double *Op = O + (int64_t)(pin ? pb : 0) * S;
+                    const double cap = m.pcap;
+                    // four scenarios per lane per step: every LDS read of
+                    // the step is issued before the arithmetic, which is
+                    // branch-free
+                    for (int32_t s0 = 0; s0 < S; s0 += 256) {
+                        float vs[4];
+                        double ns[4], ot[4], op[4];
+                        uint32_t ow[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int32_t sj = s0 + lane + 64 * j;
+                            const int32_t sc = sj < S ? sj : 0;
+                            vs[j] = vb[sc];
+                            ns[j] = Ns[sc];
+                            ot[j] = Ot[sc];
+                            op[j] = Op[sc];
+                            ow[j] = ob[sc >> 5];
+                        }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int32_t sj = s0 + lane + 64 * j;
+                            const bool ok = sj < S;
+                            const bool in = ok && ((ow[j] >> (sj & 31)) & 1u);
+                            cp += ok ? (ns[j] - mu) * (double)vs[j] : 0.0;
+                            const double a = hinge64(ot[j] + ton, cap) - hinge64(ot[j], cap);
+                            const double r = hinge64(op[j] - ton, cap) - hinge64(op[j], cap);
+                            pen += (in && tin ? a : 0.0) + (in && pin ? r : 0.0);
+                            viol |= in && tin && ot[j] + ton > cap;
                         }
                     }
                     const double c = wave_sum(cp) / S;

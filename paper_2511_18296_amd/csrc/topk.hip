@@ -146,18 +146,34 @@ __global__ void __launch_bounds__(256) k_hist0(const float *score, const uint8_t
     const bool take_all = res[0] < 0 || res[2] <= k_rem;
     const int sel = take_all ? -1 : res[0];
     // per-replica region sizes: items above sel (all items with take_all)
-    // and items on sel
-    if (threadIdx.x < kRep) {
-        const int r = threadIdx.x;
-        int32_t above = 0, equal = 0;
-        for (int b = sel + 1; b < kBins; ++b)
-            above += (int32_t)__hip_atomic_load(w.hist + (size_t)r * kBins + b, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-        if (sel >= 0)
-            equal = (int32_t)__hip_atomic_load(w.hist + (size_t)r * kBins + sel,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        part[r] = (uint32_t)above;
-        part[kRep + r] = (uint32_t)equal;
+    // and items on sel; every thread takes its bins of every replica (all
+    // loads in flight together) and the sums meet in LDS
+    if (threadIdx.x < 2 * kRep) part[threadIdx.x] = 0u;
+    __syncthreads();
+    {
+        constexpr int kPer = kBins / 256;
+        uint32_t above[kRep], equal[kRep];
+#pragma unroll
+        for (int r = 0; r < kRep; ++r) {
+            above[r] = 0u;
+            equal[r] = 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int b = threadIdx.x + 256 * j;
+#pragma unroll
+            for (int r = 0; r < kRep; ++r) {
+                const uint32_t h = __hip_atomic_load(w.hist + (size_t)r * kBins + b,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                above[r] += b > sel ? h : 0u;
+                equal[r] += b == sel ? h : 0u;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kRep; ++r) {
+            if (above[r]) atomicAdd(&part[r], above[r]);
+            if (equal[r]) atomicAdd(&part[kRep + r], equal[r]);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -232,10 +248,11 @@ __global__ void __launch_bounds__(256) k_compact0(const float *score, const uint
     }
 }
 
-// One workgroup: while the chosen keys plus the candidates exceed kSortCap,
-// refine the candidates by the next digit; then sort chosen and candidate
-// keys together (keys are unique, so the first min(k, total) of the sorted
-// union are exactly the top k) and write the outputs.
+// One workgroup: while the candidates on the boundary digit are more than the
+// keys still needed, refine them by the next digit; then every remaining
+// candidate is needed, and the chosen keys plus the remaining candidates are
+// exactly the top min(k, total) (keys are unique).  They are sorted (at most
+// k <= kSortCap keys, in LDS) and written out.
 constexpr int kSortCap = 8192;
 
 __global__ void __launch_bounds__(kRefineThreads) k_refine_sort(TopkWs w, int32_t k,
@@ -257,7 +274,9 @@ __global__ void __launch_bounds__(kRefineThreads) k_refine_sort(TopkWs w, int32_
     uint64_t *src = w.cand0, *dst = w.cand1;
     for (int level = 1; level < kLevels; ++level) {
         const int32_t ns = n_src_s;
-        if (ns == 0 || n_out_s + ns <= kSortCap) break;
+        // stop once every remaining candidate is needed: the sort then
+        // takes exactly the k chosen keys
+        if (ns == 0 || ns <= k_rem_s) break;
         const int nb = 1 << c_bits[level];
         for (int i = tid; i < nb; i += kRefineThreads) lh[i] = 0;
         if (tid == 0) n_dst_s = 0;
