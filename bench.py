@@ -27,6 +27,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the exhaustive evaluation kernel, measured with
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE and scaled by what the same
+# counters read for a device copy of known size (profiles/ holds the
+# summaries).  Keyed by the SHA-1 of the kernel's sources: a changed kernel
+# reports null until it is measured again.
+MEASURED_TRAFFIC = {}
+EVAL_SOURCES = ("eval.hip", "eval_dev.h", "internal.h")
+
+
+def eval_source_sha():
+    import hashlib
+    h = hashlib.sha1()
+    for f in EVAL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2511_18296_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -151,6 +168,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-search", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the steps, copy a device buffer of MIB MiB three times "
+                         "(the reference kernel for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -163,6 +183,15 @@ def main():
     from paper_2511_18296_amd.binding import Model, MoveSet, TopK
 
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_calibration} MiB")
+        del src, dst
     log("generating the 54,000-block instance ...")
     inst = mpsgen.largest_plain()
     N, S, T = inst.N, inst.S, inst.T
@@ -241,7 +270,8 @@ def main():
                    "copies_rotated": args.copies},
         "roofline": {"kernel": "k_eval_exh", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": B},
+                     "traffic": MEASURED_TRAFFIC.get(eval_source_sha()),
+                     "bytes_per_launch": B, "source_sha1": eval_source_sha()},
         "phases_us": {"restore": t_rest * 1e6, "eval": t_eval * 1e6, "topk": t_topk * 1e6,
                       "repair": t_rep * 1e6},
         "eval_move_scenario_evals_per_s": M * S / t_eval,

@@ -13,10 +13,12 @@
 //   2. one pass moves items above the boundary digit to the output and items
 //      on it to a candidate buffer (wave-aggregated appends);
 //   3. one workgroup refines the candidates digit by digit (11/10/11/11/10
-//      more bits) until chosen keys and candidates fit in LDS together, then
-//      sorts that union with a bitonic network whose strides below 64 need
-//      no workgroup barrier.
-// Four launches in all; every count is an integer, so the result does not
+//      more bits) until every remaining candidate is needed, and appends
+//      them to the chosen keys: exactly the top min(k, total);
+//   4. each chosen key's rank is the number of chosen keys above it,
+//      counted tile against tile by a grid of workgroups, and the key is
+//      written at its rank.
+// Six launches in all; every count is an integer, so the result does not
 // depend on thread timing.
 #include <float.h>
 #include <math.h>
@@ -42,6 +44,7 @@ struct TopkCtrl {
     uint32_t done;      // workgroups finished with the level-0 histogram
     int32_t out_next[kRep];    // next free slot of each replica's output region
     int32_t cand_next[kRep];   // next free slot of each replica's candidate region
+    int32_t n_final;           // keys of the result, all in out[]
 };
 
 struct TopkWs {
@@ -50,14 +53,20 @@ struct TopkWs {
     uint64_t *out;    // [k]
     uint64_t *cand0;  // [n]
     uint64_t *cand1;  // [n]
+    uint32_t *rank_part;   // [ceil(k/256)][k] partial ranks
 };
+
+constexpr int kRankTile = 256;   // keys per rank workgroup and per comparison tile
+
+__host__ __device__ inline int32_t rank_tiles(int32_t k) { return (k + kRankTile - 1) / kRankTile; }
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t topk_ws_bytes(int64_t n, int32_t k) {
     const size_t nn = n > 0 ? (size_t)n : 1;
     return a256(sizeof(TopkCtrl)) + a256(sizeof(uint32_t) * kBins * kRep) +
-           a256(sizeof(uint64_t) * (size_t)k) + 2 * a256(sizeof(uint64_t) * nn);
+           a256(sizeof(uint64_t) * (size_t)k) + 2 * a256(sizeof(uint64_t) * nn) +
+           a256(sizeof(uint32_t) * (size_t)rank_tiles(k) * k);
 }
 
 static TopkWs carve_ws(void *ws, int64_t n, int32_t k) {
@@ -73,6 +82,8 @@ static TopkWs carve_ws(void *ws, int64_t n, int32_t k) {
     w.cand0 = (uint64_t *)p;
     p += a256(sizeof(uint64_t) * nn);
     w.cand1 = (uint64_t *)p;
+    p += a256(sizeof(uint64_t) * nn);
+    w.rank_part = (uint32_t *)p;
     return w;
 }
 
@@ -251,14 +262,9 @@ __global__ void __launch_bounds__(256) k_compact0(const float *score, const uint
 // One workgroup: while the candidates on the boundary digit are more than the
 // keys still needed, refine them by the next digit; then every remaining
 // candidate is needed, and the chosen keys plus the remaining candidates are
-// exactly the top min(k, total) (keys are unique).  They are sorted (at most
-// k <= kSortCap keys, in LDS) and written out.
-constexpr int kSortCap = 8192;
+// exactly the top min(k, total) (keys are unique).
 
-__global__ void __launch_bounds__(kRefineThreads) k_refine_sort(TopkWs w, int32_t k,
-                                                                int64_t *idx, float *top_score,
-                                                                int32_t *count) {
-    extern __shared__ uint64_t keys[];   // [kSortCap]
+__global__ void __launch_bounds__(kRefineThreads) k_refine(TopkWs w) {
     __shared__ uint32_t lh[kBins];
     __shared__ uint32_t part[256];
     __shared__ int32_t res[3];
@@ -314,49 +320,47 @@ __global__ void __launch_bounds__(kRefineThreads) k_refine_sort(TopkWs w, int32_
     }
     __threadfence_block();
     __syncthreads();
-    // sort the union of chosen and remaining candidate keys, descending
+    // every remaining candidate is chosen: append them after the others
     const int32_t no = n_out_s, ns = n_src_s;
-    const int32_t tot = no + ns;   // <= kSortCap here
-    int32_t P = 2;
-    while (P < tot) P <<= 1;
-    for (int i = tid; i < P; i += kRefineThreads)
-        keys[i] = i < no ? w.out[i] : (i < tot ? src[i - no] : 0ull);
+    for (int32_t i = tid; i < ns; i += kRefineThreads) w.out[no + i] = src[i];
+    if (tid == 0) w.ctrl->n_final = no + ns;
+}
+
+// Rank of each chosen key = the number of chosen keys above it (keys are
+// unique, so ranks are a permutation of 0 .. n_final-1).  Workgroup (x, y)
+// compares keys [x*256, x*256+256) with the keys of tile y staged in LDS.
+__global__ void __launch_bounds__(kRankTile) k_rank_part(TopkWs w, int32_t k) {
+    __shared__ uint64_t tile[kRankTile];
+    const int32_t tot = w.ctrl->n_final;
+    const int32_t tid = threadIdx.x;
+    const int32_t i = blockIdx.x * kRankTile + tid;
+    const int32_t j = blockIdx.y * kRankTile + tid;
+    tile[tid] = j < tot ? w.out[j] : 0ull;   // 0 is below every key
+    const uint64_t me = i < tot ? w.out[i] : ~0ull;
     __syncthreads();
-    const int32_t half = P >> 1;
-    for (int32_t size = 2, lsz = 1; size <= P; size <<= 1, ++lsz) {
-        for (int32_t stride = size >> 1, lst = lsz - 1; stride > 0; stride >>= 1, --lst) {
-            for (int32_t j = tid; j < half; j += kRefineThreads) {
-                const int32_t i = ((j >> lst) << (lst + 1)) | (j & (stride - 1));
-                const int32_t l = i + stride;
-                const bool desc = (i & size) == 0;
-                const uint64_t a = keys[i], b = keys[l];
-                if (desc ? (a < b) : (a > b)) {
-                    keys[i] = b;
-                    keys[l] = a;
-                }
-            }
-            // With a stride below 64 the pairs a wave handles lie inside its
-            // own 128 consecutive elements, so consecutive such stages need
-            // no workgroup barrier; stages with a stride of 64 or more (and
-            // the stage before one) do.
-            const int32_t next = stride > 1 ? stride >> 1 : size;
-            if (stride >= 64 || next >= 64) __syncthreads();
-            else __builtin_amdgcn_wave_barrier();
-        }
+    uint32_t c = 0;
+#pragma unroll 16
+    for (int32_t t = 0; t < kRankTile; ++t) c += tile[t] > me ? 1u : 0u;
+    if (i < k) w.rank_part[(size_t)blockIdx.y * k + i] = c;
+}
+
+// Each chosen key goes to its rank; entries past n_final get -1 / -inf.
+__global__ void __launch_bounds__(kRankTile) k_rank_scatter(TopkWs w, int32_t k, int64_t *idx,
+                                                            float *top_score, int32_t *count) {
+    const int32_t tot = w.ctrl->n_final;
+    const int32_t i = blockIdx.x * kRankTile + threadIdx.x;
+    if (i < tot) {
+        uint32_t r = 0;
+        const int32_t nt = rank_tiles(k);
+        for (int32_t t = 0; t < nt; ++t) r += w.rank_part[(size_t)t * k + i];
+        const uint64_t key = w.out[i];
+        idx[r] = (int64_t)(0xffffffffu - (uint32_t)(key & 0xffffffffull));
+        if (top_score) top_score[r] = unord_f32((uint32_t)(key >> 32));
+    } else if (i < k) {
+        idx[i] = -1;
+        if (top_score) top_score[i] = -INFINITY;
     }
-    __syncthreads();
-    const int32_t n = tot < k ? tot : k;
-    for (int i = tid; i < k; i += kRefineThreads) {
-        if (i < n) {
-            const uint64_t key = keys[i];
-            idx[i] = (int64_t)(0xffffffffu - (uint32_t)(key & 0xffffffffull));
-            if (top_score) top_score[i] = unord_f32((uint32_t)(key >> 32));
-        } else {
-            idx[i] = -1;
-            if (top_score) top_score[i] = -INFINITY;
-        }
-    }
-    if (tid == 0) *count = n;
+    if (i == 0) *count = tot;
 }
 
 hipError_t launch_topk(const float *score, const uint8_t *flags, int64_t n, int32_t k,
@@ -370,8 +374,11 @@ hipError_t launch_topk(const float *score, const uint8_t *flags, int64_t n, int3
                        w);
     hipLaunchKernelGGL(k_compact0, dim3((unsigned)g), dim3(256), 0, st, score, flags, n, req,
                        forbid, w);
-    hipLaunchKernelGGL(k_refine_sort, dim3(1), dim3(kRefineThreads),
-                       sizeof(uint64_t) * (size_t)kSortCap, st, w, k, idx, top_score, count);
+    hipLaunchKernelGGL(k_refine, dim3(1), dim3(kRefineThreads), 0, st, w);
+    const unsigned nt = (unsigned)rank_tiles(k);
+    hipLaunchKernelGGL(k_rank_part, dim3(nt, nt), dim3(kRankTile), 0, st, w, k);
+    hipLaunchKernelGGL(k_rank_scatter, dim3(nt), dim3(kRankTile), 0, st, w, k, idx, top_score,
+                       count);
     return hipGetLastError();
 }
 
