@@ -28,11 +28,12 @@
 
 namespace mps {
 
-constexpr int kWaves = 8;
+constexpr int kWaves = 8;   // candidates scored per round (a multiple of 8)
 constexpr int kThreads = 64 * kWaves;
 constexpr int kNbr = 11;   // the block, 5 predecessors, 5 successors
-constexpr int kPf = 4;     // float4 registers per thread carrying the next batch
-constexpr size_t kBatchBytes = (size_t)kPf * 16 * kThreads;   // 32 KB
+constexpr size_t kBatchBytes = 32768;   // candidate records per LDS batch buffer
+constexpr int kPf = (int)(kBatchBytes / (16 * kThreads));   // float4 per thread per batch
+static_assert(kWaves % 8 == 0 && kPf >= 1, "repair launch shape");
 
 // DPP move of a double (both 32-bit halves); lanes whose source is outside
 // the row or masked out read 0 (bound_ctrl) or keep `old` (row_mask).
@@ -114,7 +115,7 @@ __host__ __device__ inline RepairLayout repair_layout(int32_t S, int32_t T, int3
     L.hval = put(H);
     L.buf[0] = put(rb * B);
     L.buf[1] = put(rb * B);
-    L.res = put(sizeof(double) * 4 * kWaves + sizeof(int32_t) * kWaves + 8 + 64);
+    L.res = put(sizeof(double) * (3 * kWaves + 3) + sizeof(int32_t) * kWaves + kWaves + 16);
     L.total = off;
     L.B = B;
     return L;
@@ -391,9 +392,13 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
             }
             __syncthreads();
             // ---- the first accepted candidate of the round, if any: one
-            // byte per wave, read as one 64-bit word
-            const uint64_t am = *(const uint64_t *)acc & 0x0101010101010101ull;
-            const int32_t r = am ? (__builtin_ctzll(am) >> 3) : ne;
+            // byte per wave, read as 64-bit words (eight waves each)
+            int32_t r = ne;
+#pragma unroll
+            for (int q = kWaves / 8 - 1; q >= 0; --q) {
+                const uint64_t am = ((const uint64_t *)acc)[q] & 0x0101010101010101ull;
+                if (am) r = q * 8 + (__builtin_ctzll(am) >> 3);
+            }
             if (r < ne) {
                 const char *rp = bb + (size_t)(pos + r - c0) * rb;
                 const CandHdr &e = *(const CandHdr *)rp;
