@@ -63,6 +63,30 @@ __device__ __forceinline__ double wave_sum(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// wave_sum of two values at once: the two DPP chains are independent, so
+// their latencies overlap.  Same order of additions as wave_sum.
+__device__ __forceinline__ void wave_sum2(double &x, double &y) {
+    x += dpp_f64<0x111, 0xf>(x);
+    y += dpp_f64<0x111, 0xf>(y);
+    x += dpp_f64<0x112, 0xf>(x);
+    y += dpp_f64<0x112, 0xf>(y);
+    x += dpp_f64<0x114, 0xf>(x);
+    y += dpp_f64<0x114, 0xf>(y);
+    x += dpp_f64<0x118, 0xf>(x);
+    y += dpp_f64<0x118, 0xf>(y);
+    x += dpp_f64<0x142, 0xa>(x);
+    y += dpp_f64<0x142, 0xa>(y);
+    x += dpp_f64<0x143, 0xc>(x);
+    y += dpp_f64<0x143, 0xc>(y);
+    const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+    const int xl = __builtin_amdgcn_readlane((int)(bx & 0xffffffff), 63);
+    const int xh = __builtin_amdgcn_readlane((int)(bx >> 32), 63);
+    const int yl = __builtin_amdgcn_readlane((int)(by & 0xffffffff), 63);
+    const int yh = __builtin_amdgcn_readlane((int)(by >> 32), 63);
+    x = __longlong_as_double(((long long)xh << 32) | (unsigned)xl);
+    y = __longlong_as_double(((long long)yh << 32) | (unsigned)yl);
+}
+
 __device__ __forceinline__ uint32_t hslot(int32_t b, int hbits) {
     return ((uint32_t)b * 0x9E3779B1u) >> (32 - hbits);
 }
@@ -222,6 +246,7 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int32_t H = 1 << hbits;
+    const double inv_S = 1.0 / S, pen_per_S = m.pen_proc / S;
 
     int32_t n = *count;
     if (n > n_max) n = n_max;
@@ -295,6 +320,7 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
                 int32_t cur = 0;
                 bool found = false;
                 const int32_t key = lane < kNbr ? e.key[lane] : -1;
+                const int32_t p0 = lane < kNbr ? e.p0[lane] : 0;
                 if (key >= 0) {
                     uint32_t hs = hslot(key, hbits);
                     for (int32_t probe = 0; probe < H; ++probe) {
@@ -307,7 +333,7 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
                         if (kk < 0) break;
                         hs = (hs + 1) & (uint32_t)(H - 1);
                     }
-                    if (!found) cur = e.p0[lane];
+                    if (!found) cur = p0;
                 }
                 const int32_t t = e.t;
                 const int32_t pb = __shfl(cur, 0);
@@ -352,14 +378,18 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
                             const bool ok = sj < S;
                             const bool in = ok && ((ow[j] >> (sj & 31)) & 1u);
                             cp += ok ? (ns[j] - mu) * (double)vs[j] : 0.0;
-                            const double a = hinge64(ot[j] + ton, cap) - hinge64(ot[j], cap);
-                            const double r = hinge64(op[j] - ton, cap) - hinge64(op[j], cap);
-                            pen += (in && tin ? a : 0.0) + (in && pin ? r : 0.0);
-                            viol |= in && tin && ot[j] + ton > cap;
+                            // max(0, o + ton - cap) - max(0, o - cap) is the
+                            // excess added, clamp(o + ton - cap, 0, ton); the
+                            // removal from the old period likewise
+                            const double xa = ot[j] + ton - cap;
+                            const double a = fmin(fmax(xa, 0.0), ton);
+                            const double r = fmin(fmax(op[j] - cap, 0.0), ton);
+                            pen += (in && tin ? a : 0.0) - (in && pin ? r : 0.0);
+                            viol |= in && tin && xa > 0.0;
                         }
                     }
-                    const double c = wave_sum(cp) / S;
-                    pen = wave_sum(pen);
+                    wave_sum2(cp, pen);
+                    const double c = cp * inv_S;
                     viol = __ballot(viol) != 0ull;
                     const double dvar = 2.0 * dd * c + dd * dd * e.Vb;
                     var1 = fmax(var + dvar, 0.0);
@@ -369,7 +399,7 @@ __global__ void __launch_bounds__(kThreads) k_repair(DevModel m, int32_t n_max,
                     const double den = sp + sigma;
                     const double dsig = den > 0.0 ? dvar / den : 0.0;
                     const double dR = dd * e.mb - m.lambda * dsig;
-                    const double dPp = m.pen_proc * pen / S;
+                    const double dPp = pen * pen_per_S;
                     double am = 0.0;
                     bool mine_ok = true;
                     if (t < T) {

@@ -9,7 +9,8 @@
 // index), so the top k items are the k largest keys.  A most-significant-
 // digit radix select finds them:
 //   1. histogram of the top 11 bits over all items (every workgroup adds its
-//      LDS histogram; the last workgroup to finish picks the boundary digit);
+//      LDS histogram to one of eight replicas); one workgroup then picks the
+//      boundary digit;
 //   2. one pass moves items above the boundary digit to the output and items
 //      on it to a candidate buffer (wave-aggregated appends);
 //   3. one workgroup refines the candidates digit by digit (11/10/11/11/10
@@ -18,7 +19,7 @@
 //   4. each chosen key's rank is the number of chosen keys above it,
 //      counted tile against tile by a grid of workgroups, and the key is
 //      written at its rank.
-// Six launches in all; every count is an integer, so the result does not
+// Seven launches in all; every count is an integer, so the result does not
 // depend on thread timing.
 #include <float.h>
 #include <math.h>
@@ -41,7 +42,6 @@ struct TopkCtrl {
     int32_t n_cand;     // candidates on the boundary digit after level 0
     int32_t sel;        // boundary digit of level 0
     int32_t take_all;   // every qualifying item is in the top k
-    uint32_t done;      // workgroups finished with the level-0 histogram
     int32_t out_next[kRep];    // next free slot of each replica's output region
     int32_t cand_next[kRep];   // next free slot of each replica's candidate region
     int32_t n_final;           // keys of the result, all in out[]
@@ -99,7 +99,6 @@ __global__ void k_topk_init(TopkWs w, int32_t k) {
         w.ctrl->n_cand = 0;
         w.ctrl->sel = 0;
         w.ctrl->take_all = 0;
-        w.ctrl->done = 0;
     }
 }
 
@@ -107,18 +106,12 @@ __global__ void k_topk_init(TopkWs w, int32_t k) {
 // range of 256 * kItems items and issues all their loads before using them.
 constexpr int kItems = 8;
 
-// Level-0 histogram over all items.  Workgroup g adds its LDS histogram to
-// replica g % kRep; the last workgroup sums the replicas, selects the digit,
-// and lays out the output and candidate regions of each replica back to back
-// (replica r's counts are exactly the items workgroups g = r (mod kRep) will
-// append in the next pass, which covers the same items per workgroup).
+// Level-0 histogram over all items: workgroup g adds its LDS histogram to
+// replica g % kRep (spreading the global atomics over kRep copies).
 __global__ void __launch_bounds__(256) k_hist0(const float *score, const uint8_t *flags,
                                                int64_t n, uint8_t req, uint8_t forbid,
                                                TopkWs w) {
     __shared__ uint32_t lh[kBins];
-    __shared__ uint32_t part[256];
-    __shared__ int32_t res[3];
-    __shared__ int last;
     for (int i = threadIdx.x; i < kBins; i += 256) lh[i] = 0;
     const int64_t base = (int64_t)blockIdx.x * 256 * kItems + threadIdx.x;
     uint64_t key[kItems];
@@ -129,21 +122,38 @@ __global__ void __launch_bounds__(256) k_hist0(const float *score, const uint8_t
         q[u] = i < n && item_key(score, flags, i, req, forbid, key[u]);
     }
     __syncthreads();
+    // scores crowd into few digits: one LDS atomic per distinct digit of a
+    // wave (lanes grouped by ballot) instead of one per lane
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int u = 0; u < kItems; ++u)
-        if (q[u]) atomicAdd(&lh[digit_of(key[u], 0)], 1u);
+    for (int u = 0; u < kItems; ++u) {
+        const int d = q[u] ? digit_of(key[u], 0) : -1;
+        uint64_t pending = __ballot(d >= 0);
+        while (pending) {
+            const int leader = __ffsll((unsigned long long)pending) - 1;
+            const int dl = __shfl(d, leader);
+            const uint64_t same = __ballot(d == dl);
+            if (lane == leader) atomicAdd(&lh[dl], (uint32_t)__popcll(same));
+            pending &= ~same;
+        }
+    }
     __syncthreads();
     uint32_t *rep = w.hist + (size_t)(blockIdx.x % kRep) * kBins;
     for (int i = threadIdx.x; i < kBins; i += 256) {
         const uint32_t c = lh[i];
         if (c) atomicAdd(rep + i, c);
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&w.ctrl->done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+// One workgroup after the histogram launch: sum the replicas, select the
+// boundary digit and lay out the output and candidate regions of each
+// replica back to back (replica r's counts are exactly the items workgroups
+// g = r (mod kRep) of the compaction will append, which covers the same
+// items per workgroup).
+__global__ void __launch_bounds__(256) k_select0(TopkWs w) {
+    __shared__ uint32_t lh[kBins];
+    __shared__ uint32_t part[256];
+    __shared__ int32_t res[3];
     for (int i = threadIdx.x; i < kBins; i += 256) {
         uint32_t c = 0;
         for (int r = 0; r < kRep; ++r)
@@ -372,6 +382,7 @@ hipError_t launch_topk(const float *score, const uint8_t *flags, int64_t n, int3
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_hist0, dim3((unsigned)g), dim3(256), 0, st, score, flags, n, req, forbid,
                        w);
+    hipLaunchKernelGGL(k_select0, dim3(1), dim3(256), 0, st, w);
     hipLaunchKernelGGL(k_compact0, dim3((unsigned)g), dim3(256), 0, st, score, flags, n, req,
                        forbid, w);
     hipLaunchKernelGGL(k_refine, dim3(1), dim3(kRefineThreads), 0, st, w);
