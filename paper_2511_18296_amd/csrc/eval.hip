@@ -21,6 +21,9 @@
 // a tile (its rows of v, block data, ore words, tables) is issued before
 // the first wait, so a tile costs one memory round trip.  Scores and flags of
 // the tile are staged in LDS and written as one contiguous, coalesced range.
+// With at most 8 ore words (S <= 256) a lane scores its block's destinations
+// with the block invariants hoisted and each destination's table entries read
+// once per wave (score_block_fast).
 #include <float.h>
 
 #include "eval_dev.h"
@@ -65,12 +68,7 @@ __global__ void __launch_bounds__(kNT) k_eval_exh(DevModel m, int32_t D, float *
 
     const float lam = (float)m.lambda, pps = (float)(m.pen_proc / m.S);
     if (valid) {
-        auto ow = [&](int32_t w) { return L.ore[w * 64 + lane]; };
-        const float remv = removal_term(m, tv, bi.pb, bi.ton32, ow);
-        for (int32_t t = wave; t < D; t += kNW) {
-            const MoveOut o = score_move(m, tv, L.d64, L.Ms, t, bi.pb, bi.lo, bi.hi, c, remv,
-                                         bi.ton32, bi.ton64, bi.mb, bi.Vb, var32, sig32, lam,
-                                         pps, ow);
+        auto emit = [&](int32_t t, const MoveOut &o) {
             stage_s[lane * D + t] = o.score;
             stage_f[lane * D + t] = o.flags;
             if (COMP) {
@@ -79,6 +77,16 @@ __global__ void __launch_bounds__(kNT) k_eval_exh(DevModel m, int32_t D, float *
                 dPp[i] = o.dpp;
                 dPm[i] = o.dpm;
             }
+        };
+        if (m.W <= 8) {
+            score_block_fast(m, tv, L, wave, lane, bi, c, D, var32, sig32, lam, pps, emit);
+        } else {
+            auto ow = [&](int32_t w) { return L.ore[w * 64 + lane]; };
+            const float remv = removal_term(m, tv, bi.pb, bi.ton32, ow);
+            for (int32_t t = wave; t < D; t += kNW)
+                emit(t, score_move(m, tv, L.d64, L.Ms, t, bi.pb, bi.lo, bi.hi, c, remv,
+                                   bi.ton32, bi.ton64, bi.mb, bi.Vb, var32, sig32, lam, pps,
+                                   ow));
         }
     }
     __syncthreads();

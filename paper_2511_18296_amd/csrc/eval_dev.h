@@ -328,6 +328,82 @@ __device__ __forceinline__ float tile_c(const TileLds &L, int lane, int32_t S) {
     return c / (float)S;
 }
 
+// Every destination t = wave, wave + kNW, ... of one lane's block, for
+// models with at most 8 ore words (S <= 256).  The block's invariants are
+// computed once (ore words in registers, d(p_b), the processing and mining
+// terms of leaving p_b); each destination's table entries (d(t), M[t], the
+// full-add words, the near-capacity list) are the same for every lane of the
+// wave, so they are read once per wave (scalar loads).  Same definitions as
+// score_move; the risk term uses the hardware square root and reciprocal.
+// emit(t, out) receives each move.
+template <class Emit>
+__device__ __forceinline__ void score_block_fast(const DevModel &m, const TabView &tv,
+                                                 const TileLds &L, int wave, int lane,
+                                                 const BlockInfo &bi, float c, int32_t D,
+                                                 float var32, float sig32, float lam, float pps,
+                                                 Emit emit) {
+    const int32_t T = m.T, W = m.W;
+    uint32_t orw[8];
+#pragma unroll
+    for (int w = 0; w < 8; ++w) orw[w] = w < W ? L.ore[w * 64 + lane] : 0u;
+    auto ow = [&](int32_t w) { return L.ore[w * 64 + lane]; };
+    const int32_t pb = bi.pb;
+    const float remv = removal_term(m, tv, pb, bi.ton32, ow);
+    const double dpb = L.d64[pb];
+    const double mcap = m.mcap, ton = bi.ton64;
+    // mining excess removed from the old period: -clamp(M[p_b] - cap, 0, ton)
+    const double am_rem = pb < T ? -fmin(fmax(L.Ms[pb] - mcap, 0.0), ton) : 0.0;
+    for (int32_t t = wave; t < D; t += kNW) {
+        const bool noop = t == pb;
+        const float dd = (float)(gld(m.d64 + t) - dpb);
+        const float dvar = fmaf(2.0f * dd, c, dd * dd * bi.Vb);
+        const float vp = fmaxf(var32 + dvar, 0.0f);
+        const float den = __builtin_amdgcn_sqrtf(vp) + sig32;
+        const float dsig = den > 0.0f ? dvar * __builtin_amdgcn_rcpf(den) : 0.0f;
+        const float dr = fmaf(dd, bi.mb, -lam * dsig);
+        float addv = 0.0f;
+        bool viol = false, mine_ok = true;
+        double am = am_rem;
+        if (t < T) {
+            // eight words read unconditionally (one scalar load): words past
+            // W meet zero ore words, and the state arena continues after
+            // full_add (full_rem, then the lists), so the reads stay inside it
+            const uint32_t *fa = m.tab.full_add + (int64_t)t * W;
+            int32_t cnt = 0;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) cnt += __popc(orw[w] & gld(fa + w));
+            addv = (float)cnt * bi.ton32;
+            viol = cnt != 0;
+            const int32_t j1 = gld(m.tab.rng + T + t);
+            for (int32_t j = gld(m.tab.rng + t); j < j1; ++j) {
+                const AddEntry e = gld(m.tab.add_packed + j);
+                if ((ow(e.s >> 5) >> (e.s & 31)) & 1u) {
+                    addv += fmaxf(bi.ton32 - e.d, 0.0f);
+                    if (ton >= e.tau) viol = true;
+                }
+            }
+            // mining excess added to the new period: clamp(M[t] + ton - cap, 0, ton)
+            const double x = gld(m.M + t) + ton;
+            mine_ok = x <= mcap;
+            am += fmin(fmax(x - mcap, 0.0), ton);
+        }
+        MoveOut o;
+        uint8_t f = 0;
+        if (bi.lo <= t && t <= bi.hi) f |= MPS_PREC_OK;
+        if (noop || t == T || mine_ok) f |= MPS_MINE_OK;
+        if (noop || t == T || !viol) f |= MPS_PROC_OK;
+        if (noop) f |= MPS_NOOP;
+        const float dpp = noop ? 0.0f : pps * (addv - remv);
+        const float dpm = noop ? 0.0f : (float)(m.pen_mine * am);
+        o.flags = f;
+        o.dr = noop ? 0.0f : dr;
+        o.dpp = dpp;
+        o.dpm = dpm;
+        o.score = noop ? 0.0f : (dr - dpp) - dpm;
+        emit(t, o);
+    }
+}
+
 // One listed move (b, t) from the per-block quantities the list pass wrote
 // (blk_c, blk_rem, blk_info); a move out of range is BAD with score -FLT_MAX.
 __device__ __forceinline__ MoveOut list_move(const DevModel &m, const TabView &tv,
