@@ -238,8 +238,9 @@ mps_status mps_relaxed_bwd(mps_model *m, const float *x, const mps_relax_params 
 /* Workspace bytes of mps_rank_moves for k moves. */
 size_t mps_rank_ws_bytes(const mps_model *m, int32_t k);
 
-/* Gradient ranking of every non-no-op move (b, t') against the current
- * schedule: gain = Gc[b][p_b] - Gc[b][t'] with Gc[b][t] = sum_{u<t} grad_x[b][u]
+/* Gradient ranking of every non-no-op move (b, t') that keeps the current
+ * schedule precedence-feasible (Eq. 15; the others could never be applied):
+ * gain = Gc[b][p_b] - Gc[b][t'] with Gc[b][t] = sum_{u<t} grad_x[b][u]
  * (the first-order change of J along x(p') - x(p)); returns the k best
  * (gain descending, move index b*(T+1)+t' ascending) as block (int32 [k]),
  * period (int8 [k]), gain (float [k], may be NULL) and *count (device int32);

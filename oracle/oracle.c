@@ -493,11 +493,19 @@ int32_t or_rank_moves(const or_inst *I, const int8_t *p, const double *grad,
     sidx_t *a = malloc(sizeof(sidx_t) * N * D);
     double *Gc = malloc(sizeof(double) * D);
     int64_t m = 0;
+    int32_t nb[5];
     for (int64_t b = 0; b < N; ++b) {
         Gc[0] = 0.0;
         for (int32_t t = 0; t < T; ++t) Gc[t + 1] = Gc[t] + grad[b * T + t];
+        /* moves that keep the schedule precedence-feasible (Eq. 15):
+         * p[a] <= t' for every predecessor a, t' <= p[c] for every successor */
+        int32_t lo = 0, hi = T;
+        int32_t np_ = or_predecessors(I, (int32_t)b, nb);
+        for (int32_t j = 0; j < np_; ++j) if (p[nb[j]] > lo) lo = p[nb[j]];
+        int32_t ns_ = or_successors(I, (int32_t)b, nb);
+        for (int32_t j = 0; j < ns_; ++j) if (p[nb[j]] < hi) hi = p[nb[j]];
         for (int32_t t = 0; t < D; ++t) {
-            if (t == p[b]) continue;
+            if (t == p[b] || t < lo || t > hi) continue;
             a[m].s = Gc[p[b]] - Gc[t];
             a[m].i = b * D + t;
             ++m;

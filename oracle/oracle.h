@@ -82,7 +82,9 @@ double or_relaxed_d(const or_inst *I, const double *x, const or_relax_t *rp,
                     double *grad);
 
 /* Gradient ranking: first-order gain of every non-no-op move at schedule p
- * from the gradient at x(p); returns the top k (gain desc, index asc). */
+ * that keeps p precedence-feasible (Eq. 15: every predecessor a has
+ * p[a] <= t', every successor c has t' <= p[c]), from the gradient at x(p);
+ * returns the top k (gain desc, index asc). */
 int32_t or_rank_moves(const or_inst *I, const int8_t *p, const double *grad,
                       int32_t k, int32_t *block, int8_t *period, double *gain);
 

@@ -446,10 +446,14 @@ __global__ void k_rank_gains(DevModel m, const float *grad, float *gain, uint8_t
             if (t < T) run += (double)grad[b * T + t];
         }
     }
+    // only moves that keep the schedule precedence-feasible (Eq. 15) rank:
+    // the repair could never apply the others
+    int32_t lo, hi;
+    prec_window(m, m.p, (int32_t)b, lo, hi);
     double run = 0.0;
     for (int32_t t = 0; t < D; ++t) {
         gain[b * D + t] = (float)(gpb - run);
-        fl[b * D + t] = t == pb ? 0 : 1;
+        fl[b * D + t] = (t != pb && lo <= t && t <= hi) ? 1 : 0;
         if (t < T) run += (double)grad[b * T + t];
     }
 }

@@ -352,6 +352,9 @@ def test_rank_moves_is_directional_derivative(tiny):
         dx = mpsgen.integer_x(q, tiny.T).astype(np.float64) - x
         assert gain[j] == pytest.approx(float((g * dx).sum()), rel=1e-9, abs=1e-6)
         assert t[j] != p[b[j]]
+        # only precedence-feasible moves are ranked (brute force over Pred/Succ)
+        assert all(p[a] <= t[j] for a in o.predecessors(int(b[j])))
+        assert all(t[j] <= p[c] for c in o.successors(int(b[j])))
     D = tiny.T + 1
     key = [(-gain[j], int(b[j]) * D + int(t[j])) for j in range(k)]
     assert key == sorted(key)
