@@ -71,6 +71,7 @@ enum {
 #define MPS_MAX_TOPK 8192            /* k of mps_topk / mps_rank_moves */
 #define MPS_MAX_BATCH_TOPK 1024      /* k of a batch (per model) */
 #define MPS_MAX_BATCH 4096           /* models in one batch */
+#define MPS_MAX_REPAIR_SCENARIOS 1024 /* S of mps_repair and mps_search */
 
 typedef struct mps_model mps_model;
 
@@ -195,8 +196,10 @@ mps_status mps_topk(const float *score, const uint8_t *flags, int64_t n,
  * when hard_capacity != 0) and its score is > 0, updating the schedule and
  * state in place.  *applied (device int32, may be NULL) receives the number
  * of applied moves.  The state is held on chip during the walk: the call
- * returns MPS_E_INVALID_ARG when 8*S*(T+1) bytes plus a hash map of
- * 5*2*max_cand bytes exceed one workgroup's LDS; max_cand <= MPS_MAX_TOPK. */
+ * returns MPS_E_INVALID_ARG when S > MPS_MAX_REPAIR_SCENARIOS or when
+ * 8*(T+1)*S rounded up to 4 (O rows) + 16*(T+1) + 2*max_cand (period map) +
+ * two batches of candidate records (up to 40 KB each) exceed one workgroup's
+ * LDS; max_cand <= MPS_MAX_TOPK.  Calls on one model must not overlap. */
 mps_status mps_repair(mps_model *m, const mps_moves *moves,
                       const int64_t *idx, const int32_t *count,
                       int32_t max_cand, int32_t hard_capacity,

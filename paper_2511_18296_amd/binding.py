@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libmps.so")
 PREC_OK, MINE_OK, PROC_OK, NOOP, BAD = 1, 2, 4, 8, 16
 MAX_PERIODS, MAX_SCENARIOS, MAX_TOPK = 126, 4096, 8192
 MAX_BATCH_TOPK, MAX_BATCH = 1024, 4096
+MAX_REPAIR_SCENARIOS = 1024
 
 STATUS = {0: "MPS_OK", 1: "MPS_E_INVALID_ARG", 2: "MPS_E_OUT_OF_MEMORY",
           3: "MPS_E_DEVICE", 4: "MPS_E_INFEASIBLE", 5: "MPS_E_NOT_CAPTURABLE",

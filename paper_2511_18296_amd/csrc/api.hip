@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "batch.h"
+#include "repair.h"
 #include "internal.h"
 
 using namespace mps;
@@ -97,6 +98,7 @@ struct mps_model {
     double *obj_dev = nullptr;   // double[7]
     void *relax_ws = nullptr;    // partial sums of the relaxed forward pass
     void *gather = nullptr;      // candidate records of a repair walk
+    int32_t *rep_first = nullptr;   // [N] first candidate of each block in a walk; INT32_MAX between calls
     char *arena = nullptr;       // mutable search state (see mps_state_save)
     size_t arena_bytes = 0;
     int max_lds = 65536;
@@ -301,6 +303,7 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
         char *gw = nullptr;
         ALLOC(gw, repair_gather_bytes(S, W));
         m->gather = gw;
+        ALLOC(m->rep_first, N);
     }
 #undef ALLOC
     d.v = v_;
@@ -356,6 +359,9 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
         return st;
     if ((st = chk(hipMemcpyAsync(ton32, t32.data(), sizeof(float) * N, hipMemcpyHostToDevice, hs),
                   "copy of ton32")) != MPS_OK)
+        return st;
+    if ((st = chk(hipMemsetD32Async((hipDeviceptr_t)m->rep_first, INT32_MAX, (size_t)N, hs),
+                  "repair marks")) != MPS_OK)
         return st;
     if ((st = chk(hipMemcpyAsync(d64, dh.data(), sizeof(double) * (T + 1),
                                  hipMemcpyHostToDevice, hs),
@@ -505,14 +511,17 @@ mps_status mps_repair(mps_model *m, const mps_moves *moves, const int64_t *idx,
     if (!idx || !count) return fail(MPS_E_INVALID_ARG, "idx and count are required");
     if (max_cand < 0 || max_cand > MPS_MAX_TOPK)
         return fail(MPS_E_INVALID_ARG, "max_cand must be in 0..%d", MPS_MAX_TOPK);
+    if (m->d.S > kRepairMaxScen)
+        return fail(MPS_E_INVALID_ARG, "repair supports S <= %d (got %d)", kRepairMaxScen,
+                    m->d.S);
     size_t need = repair_lds_bytes(m->d, max_cand);
     if (need > (size_t)m->max_lds)
         return fail(MPS_E_INVALID_ARG,
-                    "repair state needs %zu bytes of LDS (S*T*8 + hash), device allows %d", need,
-                    m->max_lds);
+                    "repair state needs %zu bytes of LDS (O rows, period map, two record "
+                    "batches), device allows %d", need, m->max_lds);
     DeviceGuard g(m->device);
     hipError_t e = launch_repair(m->d, *moves, idx, count, max_cand, hard_capacity, applied,
-                                 m->gather, (hipStream_t)stream);
+                                 m->gather, m->rep_first, (hipStream_t)stream);
     return e == hipSuccess ? MPS_OK : dev_fail(e, "repair");
 }
 
@@ -609,6 +618,8 @@ mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_par
     const int32_t D = d.T + 1;
     const int64_t nm = d.N * D;
     if (nm >= ((int64_t)1 << 31)) return fail(MPS_E_INVALID_ARG, "too many moves");
+    if (d.S > kRepairMaxScen)
+        return fail(MPS_E_INVALID_ARG, "repair supports S <= %d (got %d)", kRepairMaxScen, d.S);
     if (repair_lds_bytes(d, k) > (size_t)m->max_lds)
         return fail(MPS_E_INVALID_ARG, "repair state does not fit in LDS");
     DeviceGuard g(m->device);
@@ -646,7 +657,8 @@ mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_par
         if (e == hipSuccess)
             e = launch_topk(score, flags, nm, k, MPS_PREC_OK, MPS_NOOP | MPS_BAD, idx, nullptr,
                             cnt, tws, hs);
-        if (e == hipSuccess) e = launch_repair(d, ex, idx, cnt, k, 0, cnt + 1, m->gather, hs);
+        if (e == hipSuccess)
+            e = launch_repair(d, ex, idx, cnt, k, 0, cnt + 1, m->gather, m->rep_first, hs);
         if (e == hipSuccess)
             e = hipMemcpyAsync(&h_applied, cnt + 1, sizeof(int32_t), hipMemcpyDeviceToHost, hs);
         if (e == hipSuccess) e = hipStreamSynchronize(hs);
@@ -662,7 +674,8 @@ mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_par
         if (e == hipSuccess)
             e = launch_topk(lscore, lflags, k, k, MPS_PREC_OK, MPS_NOOP | MPS_BAD, idx, nullptr,
                             cnt, ltws, hs);
-        if (e == hipSuccess) e = launch_repair(d, lst, idx, cnt, k, 0, cnt + 1, m->gather, hs);
+        if (e == hipSuccess)
+            e = launch_repair(d, lst, idx, cnt, k, 0, cnt + 1, m->gather, m->rep_first, hs);
         if (e == hipSuccess)
             e = hipMemcpyAsync(&h_applied, cnt + 1, sizeof(int32_t), hipMemcpyDeviceToHost, hs);
         if (e == hipSuccess) e = hipStreamSynchronize(hs);

@@ -100,12 +100,6 @@ hipError_t launch_topk(const float *score, const uint8_t *flags, int64_t n,
                        int32_t k, uint8_t req, uint8_t forbid, int64_t *idx,
                        float *top_score, int32_t *count, void *ws,
                        hipStream_t st);
-size_t repair_lds_bytes(const DevModel &m, int32_t max_cand);
-size_t repair_gather_bytes(int32_t S, int32_t W);
-hipError_t launch_repair(const DevModel &m, const mps_moves &mv,
-                         const int64_t *idx, const int32_t *count,
-                         int32_t max_cand, int32_t hard, int32_t *applied,
-                         void *gather, hipStream_t st);
 
 size_t relaxed_saved_bytes(const DevModel &m);
 size_t relaxed_ws_bytes(const DevModel &m);

@@ -27,6 +27,12 @@ def instance(name):
         return mpsgen.make_instance(13, 11, 1, 65, 4, 2.0, 78)
     if name == "single":
         return mpsgen.make_instance(6, 6, 4, 1, 6, 2.0, 79)
+    if name == "wide":
+        # S in (256, 512]: two scenario chunks per lane in the repair walk
+        return mpsgen.make_instance(10, 9, 5, 300, 7, 2.0, 81)
+    if name == "wider":
+        # S in (512, 1024], not a multiple of 4
+        return mpsgen.make_instance(8, 8, 4, 701, 5, 2.0, 82)
     if name == "tight":
         inst = mpsgen.make_instance(12, 10, 6, 96, 8, 2.0, 80)
         inst.pcap *= 0.85        # capacities bind in most periods

@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 import torch
 
+import mpsgen
 import oracle
 from gpu_common import compare_scores, gpu_model, instance, to_np
 
@@ -83,6 +84,8 @@ def test_topk_on_largest_moves_against_oracle_scores():
 
 @pytest.mark.parametrize("name,k,hard", [("tiny", 400, False), ("tiny", 400, True),
                                          ("tight", 1000, False), ("ragged", 200, True),
+                                         ("single", 150, False), ("flat", 300, False),
+                                         ("wide", 600, False), ("wider", 500, True),
                                          ("largest", 4096, False)])
 def test_repair_matches_oracle(name, k, hard):
     """Same ordered candidate list on both sides -> same accept decisions,
@@ -152,3 +155,47 @@ def test_state_save_restore_roundtrip():
     sc1, fl1 = m.eval_moves()
     assert torch.equal(sc0, sc1) and torch.equal(fl0, fl1)
     np.testing.assert_array_equal(to_np(m.get_schedule()), inst.p0)
+
+
+def test_repair_invalid_duplicate_and_repeated_calls():
+    """Invalid entries (out-of-range ids, BAD moves) are skipped, repeated
+    (block, period) pairs and repeated blocks follow the walk's rules, and a
+    second call on the changed state (the per-block marks of the first call
+    cleared) again equals the oracle walk."""
+    from paper_2511_18296_amd.binding import MoveSet
+    inst = instance("tight")
+    m = gpu_model(inst)
+    o = oracle.Oracle(inst)
+    rng = np.random.default_rng(31)
+    n_mv = 4000
+    blk = rng.integers(0, inst.N, size=n_mv).astype(np.int32)
+    per = rng.integers(0, inst.T + 1, size=n_mv).astype(np.int8)
+    blk[5], per[6] = inst.N + 3, inst.T + 1          # two BAD moves
+    blk[100:140] = blk[7]                            # one block, many periods
+    blk[200:210], per[200:210] = blk[11], per[11]    # one move repeated
+    mv = MoveSet(False, True, torch.from_numpy(blk).cuda(), torch.from_numpy(per).cuda())
+    p = inst.p0.copy()
+    for call in range(2):
+        order = rng.permutation(n_mv).astype(np.int64)[:1500]
+        order[:4] = [5, 6, -1, n_mv + 9]             # invalid ids first
+        valid = (order >= 0) & (order < n_mv)
+        ov = np.where(valid, order, 0)
+        valid &= (blk[ov] < inst.N) & (per[ov] <= inst.T)
+        idx = torch.from_numpy(order).cuda()
+        cnt = torch.tensor([len(order)], dtype=torch.int32, device="cuda")
+        applied = m.repair(mv, idx, cnt)
+        q, a, _, _ = o.repair(p, blk[ov[valid]], per[ov[valid]])
+        assert int(applied.item()) == a, call
+        np.testing.assert_array_equal(to_np(m.get_schedule()), q)
+        assert m.objective()["J"] == pytest.approx(o.objective(q)["J"], rel=1e-11)
+        p = q
+
+
+def test_repair_rejects_too_many_scenarios():
+    from paper_2511_18296_amd.binding import MoveSet, MpsError
+    inst = mpsgen.make_instance(4, 4, 2, 1100, 3, 1.5, 83)
+    m = gpu_model(inst)
+    idx = torch.zeros(4, dtype=torch.int64, device="cuda")
+    cnt = torch.tensor([4], dtype=torch.int32, device="cuda")
+    with pytest.raises(MpsError):
+        m.repair(MoveSet(), idx, cnt)
