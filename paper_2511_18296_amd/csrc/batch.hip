@@ -166,6 +166,33 @@ __device__ void sort_desc(uint64_t *s, int n) {
 // above the boundary to the selection and counts the next digit of the keys on
 // it; once they fit, one pass collects them and the remaining levels run on
 // chip.  Keys are unique, so the boundary narrows to exactly the keys needed.
+// Calls fn(qualifies, key) for every move of a model: 32 moves per thread
+// per step, their loads all issued before the first is used (one workgroup
+// walks a whole model, so the passes are bound by load latency).  Every
+// thread makes the same number of calls.
+template <class F>
+__device__ __forceinline__ void for_keys(const BatchInst &I, uint8_t req, uint8_t forbid, F fn) {
+    constexpr int U = 32;
+    const int64_t n = I.n;
+    for (int64_t i0 = 0; i0 < n; i0 += (int64_t)U * kBT) {
+        float sc[U];
+        uint8_t fl[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBT + threadIdx.x;
+            sc[u] = i < n ? gld(I.score + i) : 0.0f;
+            fl[u] = i < n ? gld(I.flags + i) : (uint8_t)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBT + threadIdx.x;
+            uint64_t key = 0;
+            const bool q = i < n && key_from(sc[u], fl[u], i, req, forbid, key);
+            fn(q, key);
+        }
+    }
+}
+
 __device__ void batch_topk(const BatchInst &I, char *lds, const uint32_t *ghist, int32_t k,
                            uint8_t req, uint8_t forbid) {
     SegLds L;
@@ -180,12 +207,8 @@ __device__ void batch_topk(const BatchInst &I, char *lds, const uint32_t *ghist,
     int32_t n_sel_final;
     if (total <= k) {
         // every qualifying move is selected
-        for (int64_t i0 = 0; i0 < n; i0 += kBT) {
-            const int64_t i = i0 + tid;
-            uint64_t key = 0;
-            const bool q = i < n && key_from(gld(I.score + i), gld(I.flags + i), i, req, forbid, key);
-            wave_append(q, key, L.sel, &L.cnt[0]);
-        }
+        for_keys(I, req, forbid,
+                 [&](bool q, uint64_t key) { wave_append(q, key, L.sel, &L.cnt[0]); });
         __syncthreads();
         n_sel_final = L.cnt[0];
     } else {
@@ -203,10 +226,7 @@ __device__ void batch_topk(const BatchInst &I, char *lds, const uint32_t *ghist,
             const int shp = level > 0 ? c_seg_shift[level - 1] : 64;
             const uint64_t pfx_prev = pfx >> (shp - sh);   // unused at level 0
             const uint64_t mask1 = (1ull << c_seg_bits[level + 1]) - 1ull;
-            for (int64_t i0 = 0; i0 < n; i0 += kBT) {
-                const int64_t i = i0 + tid;
-                uint64_t key = 0;
-                bool q = i < n && key_from(gld(I.score + i), gld(I.flags + i), i, req, forbid, key);
+            for_keys(I, req, forbid, [&](bool q, uint64_t key) {
                 bool above = false;
                 if (q) {
                     const uint64_t top = key >> sh;
@@ -215,7 +235,7 @@ __device__ void batch_topk(const BatchInst &I, char *lds, const uint32_t *ghist,
                     if (top == pfx) atomicAdd(&L.h[(int)((key >> sh1) & mask1)], 1u);
                 }
                 wave_append(above, key, L.sel, &L.cnt[0]);
-            }
+            });
             __syncthreads();
             select_digit(L.h, nb, need, L.part, L.res);
             need -= L.res[1];
@@ -229,15 +249,12 @@ __device__ void batch_topk(const BatchInst &I, char *lds, const uint32_t *ghist,
             const int sh = c_seg_shift[level];
             const int shp = level > 0 ? c_seg_shift[level - 1] : 64;
             const uint64_t pfx_prev = level > 0 ? pfx >> (shp - sh) : 0ull;
-            for (int64_t i0 = 0; i0 < n; i0 += kBT) {
-                const int64_t i = i0 + tid;
-                uint64_t key = 0;
-                const bool q = i < n && key_from(gld(I.score + i), gld(I.flags + i), i, req, forbid, key);
+            for_keys(I, req, forbid, [&](bool q, uint64_t key) {
                 const uint64_t top = key >> sh;
                 const bool in_prev = level == 0 || (key >> shp) == pfx_prev;
                 wave_append(q && in_prev && top > pfx, key, L.sel, &L.cnt[0]);
                 wave_append(q && top == pfx, key, L.cand[0], &L.cnt[1]);
-            }
+            });
             __syncthreads();
         }
         // refine the boundary on chip

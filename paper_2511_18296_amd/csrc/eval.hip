@@ -31,8 +31,13 @@
 namespace mps {
 
 // ---- exhaustive: one tile of 64 blocks, all D destinations ------------------
-template <bool COMP>
-__global__ void __launch_bounds__(kNT) k_eval_exh(DevModel m, int32_t D, float *score,
+// KCH = rows of v each lane keeps in flight: the smallest of the instantiated
+// sizes that covers a wave's share of S.  Up to 25 rows the kernel fits in 64
+// VGPRs, eight waves per SIMD: four workgroups per CU, so that the 844 tiles
+// of a 54,000-block model are all resident at once (at six waves per SIMD,
+// 768 are, and the rest run as a second round).
+template <bool COMP, int KCH>
+__global__ void __launch_bounds__(kNT, KCH <= 25 ? 8 : 1) k_eval_exh(DevModel m, int32_t D, float *score,
                                                   uint8_t *flags, float *dR, float *dPp,
                                                   float *dPm) {
     extern __shared__ __align__(16) char lds[];
@@ -47,14 +52,16 @@ __global__ void __launch_bounds__(kNT) k_eval_exh(DevModel m, int32_t D, float *
     const int64_t b = b0 + lane;
     const bool valid = b < m.N;
 
-    // one round trip: the wave's rows of v, tables, block data, ore words
+    // one round trip: block data (one wave loads it for the tile; the others
+    // take it from LDS), the wave's rows of v, tables, ore words.  The block
+    // loads go first, so that waiting for them does not wait for the rows.
+    BlockInfo bi{};
+    if (wave == 0 && valid) bi = load_block(m, b);
     int32_t s0, s1;
     wave_range(m, wave, s0, s1);
-    float x[kCH];
+    float x[KCH];
     issue_rows(m, b, valid, s0, s1, x);
     const TablePrefetch tp = issue_tables(m);
-    BlockInfo bi{};
-    if (valid) bi = load_block(m, b);
     uint32_t ow0 = 0;
     if (valid && wave < m.W) ow0 = m.ore[(int64_t)wave * m.N + b];
     const float var32 = m.sc->var32, sig32 = m.sc->sigma32;
@@ -63,11 +70,13 @@ __global__ void __launch_bounds__(kNT) k_eval_exh(DevModel m, int32_t D, float *
         L.ore[w * 64 + lane] = valid ? m.ore[(int64_t)w * m.N + b] : 0u;
     const TabView tv = commit_tables(m, L, tp);   // barrier inside
     L.cpart[wave * 64 + lane] = wave_dot(m, L.e, b, valid, s0, s1, x);
+    if (wave == 0 && valid) L.bs[lane] = share_block(m, tv, L, lane, bi);
     __syncthreads();
     const float c = tile_c(L, lane, m.S);
 
     const float lam = (float)m.lambda, pps = (float)(m.pen_proc / m.S);
     if (valid) {
+        const BlockShare bs = L.bs[lane];
         auto emit = [&](int32_t t, const MoveOut &o) {
             stage_s[lane * D + t] = o.score;
             stage_f[lane * D + t] = o.flags;
@@ -79,13 +88,12 @@ __global__ void __launch_bounds__(kNT) k_eval_exh(DevModel m, int32_t D, float *
             }
         };
         if (m.W <= 8) {
-            score_block_fast(m, tv, L, wave, lane, bi, c, D, var32, sig32, lam, pps, emit);
+            score_block_fast(m, tv, L, wave, lane, bs, c, D, var32, sig32, lam, pps, emit);
         } else {
             auto ow = [&](int32_t w) { return L.ore[w * 64 + lane]; };
-            const float remv = removal_term(m, tv, bi.pb, bi.ton32, ow);
             for (int32_t t = wave; t < D; t += kNW)
-                emit(t, score_move(m, tv, L.d64, L.Ms, t, bi.pb, bi.lo, bi.hi, c, remv,
-                                   bi.ton32, bi.ton64, bi.mb, bi.Vb, var32, sig32, lam, pps,
+                emit(t, score_move(m, tv, L.d64, L.Ms, t, bs.pb, bs.lo, bs.hi, c, bs.remv,
+                                   bs.ton32, bs.ton64, bs.mb, bs.Vb, var32, sig32, lam, pps,
                                    ow));
         }
     }
@@ -171,12 +179,20 @@ hipError_t launch_eval(const DevModel &m, const mps_moves &mv, float *score, uin
     if (mv.exhaustive) {
         const int32_t D = mv.include_never ? m.T + 1 : m.T;
         const size_t lds = base + a16(sizeof(float) * 64 * D) + a16((size_t)64 * D);
+        // rows per wave: up to 16 -> 16, 17..25 -> 25, more -> 32 (and a loop)
+        const int32_t rows = (m.S + kNW - 1) / kNW;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(tiles), dim3(kNT), lds, st, m, D, score, flags, dR, dPp,
+                               dPm);
+        };
         if (comp)
-            hipLaunchKernelGGL(k_eval_exh<true>, dim3(tiles), dim3(kNT), lds, st, m, D, score,
-                               flags, dR, dPp, dPm);
+            go(k_eval_exh<true, kCH>);
+        else if (rows <= 16)
+            go(k_eval_exh<false, 16>);
+        else if (rows <= 25)
+            go(k_eval_exh<false, 25>);
         else
-            hipLaunchKernelGGL(k_eval_exh<false>, dim3(tiles), dim3(kNT), lds, st, m, D, score,
-                               flags, dR, dPp, dPm);
+            go(k_eval_exh<false, kCH>);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_block_prep, dim3(tiles), dim3(kNT), base, st, m);

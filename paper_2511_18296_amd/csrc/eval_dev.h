@@ -125,6 +125,16 @@ struct BlockInfo {
     double ton64;
 };
 
+// The per-block quantities every destination of a block uses, computed once
+// per block of a tile (by one wave) and shared with the tile's other waves
+// through LDS: the block's data, its processing-capacity removal term, d(p_b)
+// and the mining excess removed from p_b.
+struct BlockShare {
+    int32_t pb, lo, hi, pad;
+    float ton32, mb, Vb, remv;
+    double ton64, dpb, am_rem;
+};
+
 // Loads of block b's data; the precedence window (lo = max p over
 // predecessors or 0, hi = min p over successors or T) comes from ten loads
 // issued unconditionally (invalid neighbours read b itself and are masked).
@@ -168,6 +178,7 @@ struct TileLds {
     int32_t *rng;     // [4][T]
     AddEntry *al;     // [kListCap]
     RemEntry *rl;     // [kListCap]
+    BlockShare *bs;   // [64]
     char *end;
 };
 
@@ -190,6 +201,7 @@ __host__ __device__ inline size_t tile_lds_layout(const DevModel &m, char *base,
     const size_t o_rg = put(sizeof(int32_t) * 4 * m.T);
     const size_t o_al = put(sizeof(AddEntry) * kListCap);
     const size_t o_rl = put(sizeof(RemEntry) * kListCap);
+    const size_t o_bs = put(sizeof(BlockShare) * 64);
     if (L) {
         L->d64 = (double *)(base + o_d);
         L->Ms = (double *)(base + o_M);
@@ -201,6 +213,7 @@ __host__ __device__ inline size_t tile_lds_layout(const DevModel &m, char *base,
         L->rng = (int32_t *)(base + o_rg);
         L->al = (AddEntry *)(base + o_al);
         L->rl = (RemEntry *)(base + o_rl);
+        L->bs = (BlockShare *)(base + o_bs);
         L->end = base + off;
     }
     return off;
@@ -278,23 +291,25 @@ __device__ __forceinline__ void wave_range(const DevModel &m, int wave, int32_t 
 }
 
 // Issue the loads of one chunk of kCH rows of v (all before any FMA).
+// Branch-free: a row past the wave's share re-reads row min(s + k, S - 1)
+// and gets weight 0 in fma_rows; a lane past the last block reads block 0.
 template <int KCH>
 __device__ __forceinline__ void issue_rows(const DevModel &m, int64_t b, bool valid, int32_t s,
                                            int32_t s1, float (&x)[KCH]) {
-    const float *vp = m.v + b;
+    const float *vp = m.v + (valid ? b : 0);
 #pragma unroll
-    for (int k = 0; k < KCH; ++k) {
-        x[k] = 0.0f;
-        if (valid && s + k < s1) x[k] = gld_nt(vp + (int64_t)(s + k) * m.N);
-    }
+    for (int k = 0; k < KCH; ++k) x[k] = gld_nt(vp + (int64_t)min(s + k, m.S - 1) * m.N);
 }
 
 template <int KCH>
 __device__ __forceinline__ float fma_rows(const float *e, int32_t s, int32_t s1,
                                           const float (&x)[KCH], float acc) {
 #pragma unroll
-    for (int k = 0; k < KCH; ++k)
-        if (s + k < s1) acc = fmaf(e[s + k], x[k], acc);
+    for (int k = 0; k < KCH; ++k) {
+        // adding 0 * x leaves acc unchanged (v is finite)
+        const float ek = s + k < s1 ? e[s + k] : 0.0f;
+        acc = fmaf(ek, x[k], acc);
+    }
     return acc;
 }
 
@@ -328,18 +343,40 @@ __device__ __forceinline__ float tile_c(const TileLds &L, int lane, int32_t S) {
     return c / (float)S;
 }
 
+// The shared quantities of the lane's block (ore words staged in L.ore,
+// tables committed).
+__device__ __forceinline__ BlockShare share_block(const DevModel &m, const TabView &tv,
+                                                  const TileLds &L, int lane,
+                                                  const BlockInfo &bi) {
+    auto ow = [&](int32_t w) { return L.ore[w * 64 + lane]; };
+    BlockShare s;
+    s.pb = bi.pb;
+    s.lo = bi.lo;
+    s.hi = bi.hi;
+    s.pad = 0;
+    s.ton32 = bi.ton32;
+    s.mb = bi.mb;
+    s.Vb = bi.Vb;
+    s.remv = removal_term(m, tv, bi.pb, bi.ton32, ow);
+    s.ton64 = bi.ton64;
+    s.dpb = L.d64[bi.pb];
+    // mining excess removed from the old period: -clamp(M[p_b] - cap, 0, ton)
+    s.am_rem = bi.pb < m.T ? -fmin(fmax(L.Ms[bi.pb] - m.mcap, 0.0), bi.ton64) : 0.0;
+    return s;
+}
+
 // Every destination t = wave, wave + kNW, ... of one lane's block, for
-// models with at most 8 ore words (S <= 256).  The block's invariants are
-// computed once (ore words in registers, d(p_b), the processing and mining
-// terms of leaving p_b); each destination's table entries (d(t), M[t], the
-// full-add words, the near-capacity list) are the same for every lane of the
-// wave, so they are read once per wave (scalar loads).  Same definitions as
-// score_move; the risk term uses the hardware square root and reciprocal.
-// emit(t, out) receives each move.
+// models with at most 8 ore words (S <= 256).  The block's invariants come
+// shared (share_block) and its ore words sit in registers; each
+// destination's table entries (d(t), M[t], the full-add words, the
+// near-capacity list) are the same for every lane of the wave, so they are
+// read once per wave (scalar loads).  Same definitions as score_move; the
+// risk term uses the hardware square root and reciprocal.  emit(t, out)
+// receives each move.
 template <class Emit>
 __device__ __forceinline__ void score_block_fast(const DevModel &m, const TabView &tv,
                                                  const TileLds &L, int wave, int lane,
-                                                 const BlockInfo &bi, float c, int32_t D,
+                                                 const BlockShare &bi, float c, int32_t D,
                                                  float var32, float sig32, float lam, float pps,
                                                  Emit emit) {
     const int32_t T = m.T, W = m.W;
@@ -348,11 +385,10 @@ __device__ __forceinline__ void score_block_fast(const DevModel &m, const TabVie
     for (int w = 0; w < 8; ++w) orw[w] = w < W ? L.ore[w * 64 + lane] : 0u;
     auto ow = [&](int32_t w) { return L.ore[w * 64 + lane]; };
     const int32_t pb = bi.pb;
-    const float remv = removal_term(m, tv, pb, bi.ton32, ow);
-    const double dpb = L.d64[pb];
+    const float remv = bi.remv;
+    const double dpb = bi.dpb;
     const double mcap = m.mcap, ton = bi.ton64;
-    // mining excess removed from the old period: -clamp(M[p_b] - cap, 0, ton)
-    const double am_rem = pb < T ? -fmin(fmax(L.Ms[pb] - mcap, 0.0), ton) : 0.0;
+    const double am_rem = bi.am_rem;
     for (int32_t t = wave; t < D; t += kNW) {
         const bool noop = t == pb;
         const float dd = (float)(gld(m.d64 + t) - dpb);
