@@ -266,7 +266,7 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
         };
         const size_t o_p = take((size_t)N), o_Ns = take(8 * (size_t)S),
                      o_O = take(8 * (size_t)T * S), o_M = take(8 * (size_t)T),
-                     o_e = take(4 * (size_t)S), o_sc = take(sizeof(DevScalars)),
+                     o_e = take(4 * ((size_t)S + 64)), o_sc = take(sizeof(DevScalars)),
                      o_fa = take(4 * (size_t)T * W), o_fr = take(4 * (size_t)T * W),
                      o_cnt = take(8 * (size_t)T), o_la = take(sizeof(AddEntry) * (size_t)T * S),
                      o_lr = take(sizeof(RemEntry) * (size_t)T * S), o_rg = take(16 * (size_t)T),

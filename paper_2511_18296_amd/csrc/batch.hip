@@ -101,7 +101,7 @@ __device__ void batch_blocks(const DevModel &m, char *lds, int32_t t0, int32_t t
         if (valid && wave == 0) bi = load_block(m, b);
         for (int32_t w = wave; w < m.W; w += kNW)
             L.ore[w * 64 + lane] = valid ? gld(m.ore + (int64_t)w * m.N + b) : 0u;
-        L.cpart[wave * 64 + lane] = wave_dot(m, L.e, b, valid, s0, s1, x);
+        L.cpart[wave * 64 + lane] = wave_dot(m, m.e32, b, valid, s0, s1, x);
         __syncthreads();
         const float c = tile_c(L, lane, m.S);
         if (wave == 0 && valid) {

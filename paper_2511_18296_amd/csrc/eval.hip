@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(kNT, KCH <= 25 ? 8 : 1) k_eval_exh(DevModel m,
     for (int32_t w = wave + kNW; w < m.W; w += kNW)
         L.ore[w * 64 + lane] = valid ? m.ore[(int64_t)w * m.N + b] : 0u;
     const TabView tv = commit_tables(m, L, tp);   // barrier inside
-    L.cpart[wave * 64 + lane] = wave_dot(m, L.e, b, valid, s0, s1, x);
+    L.cpart[wave * 64 + lane] = wave_dot(m, m.e32, b, valid, s0, s1, x);
     if (wave == 0 && valid) L.bs[lane] = share_block(m, tv, L, lane, bi);
     __syncthreads();
     const float c = tile_c(L, lane, m.S);
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(kNT) k_block_prep(DevModel m) {
     for (int32_t w = wave; w < m.W; w += kNW)
         L.ore[w * 64 + lane] = valid ? m.ore[(int64_t)w * m.N + b] : 0u;
     const TabView tv = commit_tables(m, L, tp);
-    L.cpart[wave * 64 + lane] = wave_dot(m, L.e, b, valid, s0, s1, x);
+    L.cpart[wave * 64 + lane] = wave_dot(m, m.e32, b, valid, s0, s1, x);
     __syncthreads();
     const float c = tile_c(L, lane, m.S);
     if (wave == 0 && valid) {

@@ -171,7 +171,6 @@ struct TileLds {
     double *d64;      // [T+1]
     double *Ms;       // [T]
     float *cpart;     // [kNW][64]
-    float *e;         // [S] scenario weights N_s - mu
     uint32_t *ore;    // [W][64]
     uint32_t *fa;     // [T][W]
     uint32_t *fr;     // [T][W]
@@ -194,7 +193,6 @@ __host__ __device__ inline size_t tile_lds_layout(const DevModel &m, char *base,
     const size_t o_d = put(sizeof(double) * (m.T + 1));
     const size_t o_M = put(sizeof(double) * m.T);
     const size_t o_c = put(sizeof(float) * 64 * kNW);
-    const size_t o_e = put(sizeof(float) * m.S);
     const size_t o_o = put(sizeof(uint32_t) * 64 * m.W);
     const size_t o_fa = put(sizeof(uint32_t) * m.T * m.W);
     const size_t o_fr = put(sizeof(uint32_t) * m.T * m.W);
@@ -206,7 +204,6 @@ __host__ __device__ inline size_t tile_lds_layout(const DevModel &m, char *base,
         L->d64 = (double *)(base + o_d);
         L->Ms = (double *)(base + o_M);
         L->cpart = (float *)(base + o_c);
-        L->e = (float *)(base + o_e);
         L->ore = (uint32_t *)(base + o_o);
         L->fa = (uint32_t *)(base + o_fa);
         L->fr = (uint32_t *)(base + o_fr);
@@ -225,7 +222,6 @@ struct TablePrefetch {
     double d, M;
     uint32_t fa, fr;
     int32_t rg;
-    float e;
     AddEntry ae;
     RemEntry re;
 };
@@ -239,7 +235,6 @@ __device__ __forceinline__ TablePrefetch issue_tables(const DevModel &m) {
     f.fa = tid < TW ? gld(m.tab.full_add + tid) : 0u;
     f.fr = tid < TW ? gld(m.tab.full_rem + tid) : 0u;
     f.rg = tid < 4 * T ? gld(m.tab.rng + tid) : 0;
-    f.e = tid < m.S ? gld(m.e32 + tid) : 0.0f;
     f.ae = gld(m.tab.add_packed + min(tid, kListCap - 1));
     f.re = gld(m.tab.rem_packed + min(tid, kListCap - 1));
     return f;
@@ -258,12 +253,10 @@ __device__ __forceinline__ TabView commit_tables(const DevModel &m, const TileLd
         L.fr[tid] = f.fr;
     }
     if (tid < 4 * T) L.rng[tid] = f.rg;
-    if (tid < m.S) L.e[tid] = f.e;
     for (int i = tid + kNT; i < TW; i += kNT) {   // tables beyond one word per thread
         L.fa[i] = gld(m.tab.full_add + i);
         L.fr[i] = gld(m.tab.full_rem + i);
     }
-    for (int i = tid + kNT; i < m.S; i += kNT) L.e[i] = gld(m.e32 + i);
     if (tid < kListCap) {
         L.al[tid] = f.ae;
         L.rl[tid] = f.re;
@@ -301,14 +294,22 @@ __device__ __forceinline__ void issue_rows(const DevModel &m, int64_t b, bool va
     for (int k = 0; k < KCH; ++k) x[k] = gld_nt(vp + (int64_t)min(s + k, m.S - 1) * m.N);
 }
 
+// e: the scenario weights in global memory, padded by 64 entries past S, so
+// that the KCH reads at s.. are in bounds; the wave-uniform reads are scalar
+// loads, the entries past the wave's share are replaced by 0 before use.
 template <int KCH>
 __device__ __forceinline__ float fma_rows(const float *e, int32_t s, int32_t s1,
                                           const float (&x)[KCH], float acc) {
+    if (s1 - s >= KCH) {   // the whole chunk is the wave's (uniform)
+#pragma unroll
+        for (int k = 0; k < KCH; ++k) acc = fmaf(gld(e + s + k), x[k], acc);
+        return acc;
+    }
 #pragma unroll
     for (int k = 0; k < KCH; ++k) {
         // adding 0 * x leaves acc unchanged (v is finite)
-        const float ek = s + k < s1 ? e[s + k] : 0.0f;
-        acc = fmaf(ek, x[k], acc);
+        const float ek = gld(e + s + k);
+        acc = fmaf(s + k < s1 ? ek : 0.0f, x[k], acc);
     }
     return acc;
 }
@@ -329,7 +330,7 @@ __device__ __forceinline__ float wave_dot(const DevModel &m, const float *e, int
                 y[k] = s + k < s1 ? gld_nt(vp + (int64_t)(s + k) * m.N) : 0.0f;
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                if (s + k < s1) acc = fmaf(e[s + k], y[k], acc);
+                if (s + k < s1) acc = fmaf(gld(e + s + k), y[k], acc);
         }
     }
     return acc;

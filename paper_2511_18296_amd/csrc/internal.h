@@ -75,7 +75,7 @@ struct DevModel {
     double *Ns;            // [S] per-scenario NPV
     double *O;             // [T][S] ore tonnage per period and scenario
     double *M;             // [T] tonnage per period
-    float *e32;            // [S] N_s - mu
+    float *e32;            // [S] N_s - mu (the allocation has 64 more entries)
     DevScalars *sc;
     const double *d64;     // [T+1] discount factors, d[T] = 0
     PeriodTables tab;
