@@ -782,6 +782,10 @@ struct mps_batch {
         bl.forbid = forbid;
         bl.grid1 = grid(n_items1);
         bl.grid2 = grid(n_items2);
+        // the top-k passes claim about 16K moves at a time
+        int32_t mpi_min = 1 << 30;
+        for (const mps_tuning &tu : tune) mpi_min = std::min(mpi_min, tu.moves_per_item);
+        bl.claim = std::max(1, 16384 / std::max(1, mpi_min));
         bl.lds_bytes = lds;
         return bl;
     }

@@ -4,16 +4,27 @@
 // the metaheuristic of Alg. 2 produces: one schedule per individual, each with
 // its own candidate list).
 //
-// Three persistent launches, each over its own queue of work items (largest
-// model first), taken by resident workgroups from an atomic counter:
+// Persistent launches over queues of work items (largest model first), taken
+// by resident workgroups from an atomic counter, and small launches of one
+// workgroup per model:
 //   1. block items (model i, item j): the per-block quantities of the list
 //      pass (c_b, removal term, precedence window) for tiles [j*tpi, j*tpi+tpi)
 //      of 64 blocks, written to the model's block workspace;
 //   2. move items (model i, item j): moves [j*mpi, j*mpi+mpi) of model i
 //      scored and flagged, with the top 12 bits of their top-k keys counted
 //      into the model's level-0 histogram;
-//   3. one workgroup per model: the exact top k of the model from that
-//      histogram (the key and order of mps_topk).
+//   3. the exact top k of every model (the key and order of mps_topk), by a
+//      radix select whose passes over the moves are again move items:
+//      a. per model, the level-0 boundary digit from that histogram;
+//      b. move items of models whose boundary digit holds more than kSegCap
+//         keys: keys above it are selected, the next 11 bits of the keys on
+//         it are counted;
+//      c. per model, the level-1 boundary digit;
+//      d. move items: the remaining selected keys and the boundary keys
+//         (at most kSegCap) are gathered;
+//      e. per model: the boundary refined on chip, the k keys sorted.
+//      A model with more than kSegCap keys sharing its top 23 key bits is
+//      walked by one workgroup instead (e).
 // The launch boundaries order the phases; no workgroup ever waits on another.
 //
 // Per-model tuning (from the autotuner, or defaults): tiles per block item,
@@ -26,7 +37,6 @@
 namespace mps {
 
 constexpr int kBT = kNT;                 // threads per persistent workgroup
-constexpr int kSegCap = 1024;            // boundary keys refined in LDS
 constexpr int kSegLevels = 6;
 __constant__ int c_seg_shift[kSegLevels] = {52, 41, 30, 19, 8, 0};
 __constant__ int c_seg_bits[kSegLevels] = {12, 11, 11, 11, 11, 8};
@@ -75,6 +85,7 @@ size_t batch_lds_bytes(const DevModel &m) {
     return moves > seg ? moves : seg;
 }
 
+// Clears the queue heads, histograms and per-model states.
 __global__ void k_batch_init(uint32_t *ctl, int64_t nwords) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -193,6 +204,70 @@ __device__ __forceinline__ void for_keys(const BatchInst &I, uint8_t req, uint8_
     }
 }
 
+// On-chip refinement of the boundary keys L.cand[0][0, L.cnt[1]), whose
+// digits down to `level` equal the boundary's, until exactly `need` of them
+// are selected: the keys above each level's boundary digit join L.sel.
+// Returns the number of keys in L.sel.  Called by every thread.
+__device__ int32_t refine_chip(const SegLds &L, int level, int32_t need) {
+    const int tid = threadIdx.x;
+    int cb = 0;
+    while (need < L.cnt[1 + cb] && level + 1 < kSegLevels) {
+        const int nb = 1 << c_seg_bits[level + 1];
+        const int sh1 = c_seg_shift[level + 1];
+        const uint64_t mask1 = (1ull << c_seg_bits[level + 1]) - 1ull;
+        const int32_t nc = L.cnt[1 + cb];
+        const uint64_t *src = cb ? L.cand[1] : L.cand[0];
+        uint64_t *dst = cb ? L.cand[0] : L.cand[1];
+        for (int j = tid; j < nb; j += kBT) L.h[j] = 0u;
+        if (tid == 0) L.cnt[2 - cb] = 0;
+        __syncthreads();
+        for (int j = tid; j < nc; j += kBT)
+            atomicAdd(&L.h[(int)((src[j] >> sh1) & mask1)], 1u);
+        __syncthreads();
+        select_digit(L.h, nb, need, L.part, L.res);
+        const uint64_t dsel = (uint64_t)L.res[0];
+        need -= L.res[1];
+        for (int j0 = 0; j0 < nc; j0 += kBT) {
+            const int j = j0 + tid;
+            const uint64_t key = j < nc ? src[j] : 0ull;
+            const uint64_t d = (key >> sh1) & mask1;
+            wave_append(j < nc && d > dsel, key, L.sel, &L.cnt[0]);
+            wave_append(j < nc && d == dsel, key, dst, &L.cnt[2 - cb]);
+        }
+        __syncthreads();
+        cb = 1 - cb;
+        ++level;
+    }
+    // the remaining boundary keys are exactly the ones still needed
+    const int32_t nc = L.cnt[1 + cb];
+    const int32_t ns = L.cnt[0];
+    const uint64_t *last = cb ? L.cand[1] : L.cand[0];
+    for (int j = tid; j < nc; j += kBT) L.sel[ns + j] = last[j];
+    __syncthreads();
+    return ns + nc;
+}
+
+// Sorts L.sel[0, n_sel_final) descending and writes the model's top k.
+__device__ void write_topk(const BatchInst &I, const SegLds &L, int32_t n_sel_final, int32_t k) {
+    const int tid = threadIdx.x;
+    int P = 2;
+    while (P < n_sel_final) P <<= 1;
+    for (int j = n_sel_final + tid; j < P; j += kBT) L.sel[j] = 0ull;
+    __syncthreads();
+    sort_desc(L.sel, P);
+    for (int j = tid; j < k; j += kBT) {
+        if (j < n_sel_final) {
+            const uint64_t key = L.sel[j];
+            gst(I.top_idx + j, (int64_t)(0xffffffffu - (uint32_t)(key & 0xffffffffu)));
+            if (I.top_score) gst(I.top_score + j, unord_f32((uint32_t)(key >> 32)));
+        } else {
+            gst(I.top_idx + j, (int64_t)-1);
+            if (I.top_score) gst(I.top_score + j, -INFINITY);
+        }
+    }
+    if (tid == 0) gst(I.top_count, n_sel_final);
+}
+
 __device__ void batch_topk(const BatchInst &I, char *lds, const uint32_t *ghist, int32_t k,
                            uint8_t req, uint8_t forbid) {
     SegLds L;
@@ -257,59 +332,9 @@ __device__ void batch_topk(const BatchInst &I, char *lds, const uint32_t *ghist,
             });
             __syncthreads();
         }
-        // refine the boundary on chip
-        int cb = 0;
-        while (need < L.cnt[1 + cb] && level + 1 < kSegLevels) {
-            const int nb = 1 << c_seg_bits[level + 1];
-            const int sh1 = c_seg_shift[level + 1];
-            const uint64_t mask1 = (1ull << c_seg_bits[level + 1]) - 1ull;
-            const int32_t nc = L.cnt[1 + cb];
-            const uint64_t *src = cb ? L.cand[1] : L.cand[0];
-            uint64_t *dst = cb ? L.cand[0] : L.cand[1];
-            for (int j = tid; j < nb; j += kBT) L.h[j] = 0u;
-            if (tid == 0) L.cnt[2 - cb] = 0;
-            __syncthreads();
-            for (int j = tid; j < nc; j += kBT)
-                atomicAdd(&L.h[(int)((src[j] >> sh1) & mask1)], 1u);
-            __syncthreads();
-            select_digit(L.h, nb, need, L.part, L.res);
-            const uint64_t dsel = (uint64_t)L.res[0];
-            need -= L.res[1];
-            for (int j0 = 0; j0 < nc; j0 += kBT) {
-                const int j = j0 + tid;
-                const uint64_t key = j < nc ? src[j] : 0ull;
-                const uint64_t d = (key >> sh1) & mask1;
-                wave_append(j < nc && d > dsel, key, L.sel, &L.cnt[0]);
-                wave_append(j < nc && d == dsel, key, dst, &L.cnt[2 - cb]);
-            }
-            __syncthreads();
-            cb = 1 - cb;
-            ++level;
-        }
-        // the remaining boundary keys are exactly the ones still needed
-        const int32_t nc = L.cnt[1 + cb];
-        const int32_t ns = L.cnt[0];
-        const uint64_t *last = cb ? L.cand[1] : L.cand[0];
-        for (int j = tid; j < nc; j += kBT) L.sel[ns + j] = last[j];
-        __syncthreads();
-        n_sel_final = ns + nc;
+        n_sel_final = refine_chip(L, level, need);
     }
-    int P = 2;
-    while (P < n_sel_final) P <<= 1;
-    for (int j = n_sel_final + tid; j < P; j += kBT) L.sel[j] = 0ull;
-    __syncthreads();
-    sort_desc(L.sel, P);
-    for (int j = tid; j < k; j += kBT) {
-        if (j < n_sel_final) {
-            const uint64_t key = L.sel[j];
-            gst(I.top_idx + j, (int64_t)(0xffffffffu - (uint32_t)(key & 0xffffffffu)));
-            if (I.top_score) gst(I.top_score + j, unord_f32((uint32_t)(key >> 32)));
-        } else {
-            gst(I.top_idx + j, (int64_t)-1);
-            if (I.top_score) gst(I.top_score + j, -INFINITY);
-        }
-    }
-    if (tid == 0) gst(I.top_count, n_sel_final);
+    write_topk(I, L, n_sel_final, k);
 }
 
 // Take the next item of a queue: one atomic per workgroup, broadcast in LDS.
@@ -359,29 +384,264 @@ __global__ void __launch_bounds__(kBT) k_batch_moves(const BatchInst *insts, con
     }
 }
 
-// One workgroup per model, largest model first.
-__global__ void __launch_bounds__(kBT) k_batch_topk(const BatchInst *insts, const int32_t *order,
-                                                    const uint32_t *ghist_all, int32_t k,
+// ---- phase 3 with the passes as move items ----------------------------------
+// Calls fn(qualifies, key) for every move of [i0, i1) of a model, eight moves
+// per thread per step with their loads issued first.  Every thread of the
+// workgroup makes the same number of calls.
+template <class F>
+__device__ __forceinline__ void for_keys_range(const BatchInst &I, int64_t i0, int64_t i1,
+                                               uint8_t req, uint8_t forbid, F fn) {
+    constexpr int U = 8;
+    for (int64_t j0 = i0; j0 < i1; j0 += (int64_t)U * kBT) {
+        float sc[U];
+        uint8_t fl[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = j0 + (int64_t)u * kBT + threadIdx.x;
+            sc[u] = i < i1 ? gld(I.score + i) : 0.0f;
+            fl[u] = i < i1 ? gld(I.flags + i) : (uint8_t)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = j0 + (int64_t)u * kBT + threadIdx.x;
+            uint64_t key = 0;
+            const bool q = i < i1 && key_from(sc[u], fl[u], i, req, forbid, key);
+            fn(q, key);
+        }
+    }
+}
+
+// wave_append into a global buffer of cap entries (a count past cap, which
+// the histograms rule out, writes nothing).
+__device__ __forceinline__ void wave_append_global(bool pred, uint64_t key, uint64_t *buf,
+                                                   int32_t *cnt, int32_t cap) {
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(cnt, (int32_t)__popcll(mask));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if (pred) {
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        const int32_t j = base + (int32_t)__popcll(mask & below);
+        if (j < cap) gst(buf + j, key);
+    }
+}
+
+// a. level-0 boundary digit of model blockIdx.x
+__global__ void __launch_bounds__(kBT) k_bt_select0(BatchCtl c, int32_t k) {
+    __shared__ uint32_t h[kSegBins];
+    __shared__ uint32_t part[4];
+    __shared__ int32_t res[4];
+    const int32_t i = blockIdx.x;
+    const uint32_t *g = c.hist0 + (int64_t)i * kSegBins;
+    for (int j = threadIdx.x; j < kSegBins; j += kBT) h[j] = g[j];
+    __syncthreads();
+    select_digit(h, kSegBins, k, part, res);   // barriers inside
+    if (threadIdx.x == 0) {
+        BtState &s = c.state[i];
+        if (res[2] <= k) {
+            s.mode = kBtTakeAll;
+            s.need = 0;
+        } else {
+            const int32_t d0 = res[0];
+            s.d0 = (uint32_t)d0;
+            s.need = k - res[1];
+            s.mode = h[d0] <= (uint32_t)kSegCap ? kBtCollect0 : kBtPass1;
+        }
+    }
+}
+
+// Take the next claim of g consecutive items of a queue.
+__device__ __forceinline__ int32_t next_claim(uint32_t *head, int32_t g, int32_t *slot) {
+    if (threadIdx.x == 0) *slot = (int32_t)atomicAdd(head, (uint32_t)g);
+    __syncthreads();
+    const int32_t q = *slot;
+    __syncthreads();
+    return q;
+}
+
+// Calls fn(model, i0, i1) for the claimed items [q0, q1), with consecutive
+// items of one model merged into one range of its moves (uniform).
+template <class F>
+__device__ __forceinline__ void for_runs(const BatchInst *insts, const int2 *items, int32_t q0,
+                                         int32_t q1, F fn) {
+    int32_t model = -1;
+    int64_t i0 = 0, i1 = 0;
+    for (int32_t q = q0; q < q1; ++q) {
+        const int2 it = items[q];
+        const BatchInst &I = insts[it.x];
+        const int64_t a = (int64_t)it.y * I.moves_per_item;
+        const int64_t b = min(I.n, a + I.moves_per_item);
+        if (it.x == model && a == i1) {
+            i1 = b;
+            continue;
+        }
+        if (model >= 0) fn(model, i0, i1);
+        model = it.x;
+        i0 = a;
+        i1 = b;
+    }
+    if (model >= 0) fn(model, i0, i1);
+}
+
+// b. move items of models in kBtPass1: keys above the level-0 boundary are
+// selected, the next 11 bits of the keys on it counted.  A claim takes g
+// consecutive items; the LDS histogram is flushed when the model changes.
+__global__ void __launch_bounds__(kBT) k_bt_pass1(const BatchInst *insts, const int2 *items,
+                                                  int32_t n_items, int32_t g, BatchCtl c,
+                                                  uint8_t req, uint8_t forbid) {
+    __shared__ uint32_t h[kSegBins1];
+    __shared__ int32_t s_item;
+    auto flush = [&](int32_t model) {
+        __syncthreads();
+        uint32_t *gh = c.hist1 + (int64_t)model * kSegBins1;
+        for (int j = threadIdx.x; j < kSegBins1; j += kBT) {
+            const uint32_t v = h[j];
+            if (v) atomicAdd(gh + j, v);
+            h[j] = 0u;
+        }
+        __syncthreads();
+    };
+    for (int j = threadIdx.x; j < kSegBins1; j += kBT) h[j] = 0u;
+    for (;;) {
+        const int32_t q0 = next_claim(c.head + 2, g, &s_item);
+        if (q0 >= n_items) break;
+        for_runs(insts, items, q0, min(n_items, q0 + g), [&](int32_t model, int64_t i0, int64_t i1) {
+            BtState &st = c.state[model];
+            if (gld(&st.mode) != kBtPass1) return;   // uniform
+            const BatchInst &I = insts[model];
+            const uint64_t d0 = gld(&st.d0);
+            uint64_t *sel = c.sel + (int64_t)model * MPS_MAX_BATCH_TOPK;
+            for_keys_range(I, i0, i1, req, forbid, [&](bool qk, uint64_t key) {
+                const uint64_t top = key >> 52;
+                wave_append_global(qk && top > d0, key, sel, &st.n_sel, MPS_MAX_BATCH_TOPK);
+                if (qk && top == d0) atomicAdd(&h[(int)((key >> 41) & (kSegBins1 - 1))], 1u);
+            });
+            flush(model);
+        });
+    }
+}
+
+// c. level-1 boundary digit of model blockIdx.x (models in kBtPass1)
+__global__ void __launch_bounds__(kBT) k_bt_select1(BatchCtl c) {
+    __shared__ uint32_t h[kSegBins1];
+    __shared__ uint32_t part[4];
+    __shared__ int32_t res[4];
+    const int32_t i = blockIdx.x;
+    BtState &s = c.state[i];
+    if (gld(&s.mode) != kBtPass1) return;   // uniform
+    const int32_t need = gld(&s.need);
+    const uint32_t *g = c.hist1 + (int64_t)i * kSegBins1;
+    for (int j = threadIdx.x; j < kSegBins1; j += kBT) h[j] = g[j];
+    __syncthreads();
+    select_digit(h, kSegBins1, need, part, res);   // barriers inside
+    if (threadIdx.x == 0) {
+        const int32_t d1 = res[0];
+        s.d1 = (uint32_t)d1;
+        s.need = need - res[1];
+        s.mode = h[d1] <= (uint32_t)kSegCap ? kBtCollect1 : kBtFallback;
+    }
+}
+
+// d. move items: the keys still to select and the boundary keys
+__global__ void __launch_bounds__(kBT) k_bt_collect(const BatchInst *insts, const int2 *items,
+                                                    int32_t n_items, int32_t g, BatchCtl c,
                                                     uint8_t req, uint8_t forbid) {
+    __shared__ int32_t s_item;
+    for (;;) {
+        const int32_t q0 = next_claim(c.head + 3, g, &s_item);
+        if (q0 >= n_items) break;
+        for_runs(insts, items, q0, min(n_items, q0 + g), [&](int32_t model, int64_t i0, int64_t i1) {
+        BtState &st = c.state[model];
+        const int32_t mode = gld(&st.mode);
+        if (mode != kBtTakeAll && mode != kBtCollect0 && mode != kBtCollect1) return;
+        const BatchInst &I = insts[model];
+        const uint64_t d0 = gld(&st.d0), d1 = gld(&st.d1);
+        uint64_t *sel = c.sel + (int64_t)model * MPS_MAX_BATCH_TOPK;
+        uint64_t *cand = c.cand + (int64_t)model * kSegCap;
+        for_keys_range(I, i0, i1, req, forbid, [&](bool qk, uint64_t key) {
+            const uint64_t top = key >> 52, mid = (key >> 41) & (kSegBins1 - 1);
+            bool s_, c_;
+            if (mode == kBtTakeAll) {
+                s_ = qk;
+                c_ = false;
+            } else if (mode == kBtCollect0) {
+                s_ = qk && top > d0;
+                c_ = qk && top == d0;
+            } else {
+                s_ = qk && top == d0 && mid > d1;
+                c_ = qk && top == d0 && mid == d1;
+            }
+            wave_append_global(s_, key, sel, &st.n_sel, MPS_MAX_BATCH_TOPK);
+            wave_append_global(c_, key, cand, &st.n_cand, kSegCap);
+        });
+        });
+    }
+}
+
+// e. one workgroup per model, largest model first: the boundary refined on
+// chip and the k keys sorted; a model in kBtFallback is walked whole.
+__global__ void __launch_bounds__(kBT) k_bt_final(const BatchInst *insts, const int32_t *order,
+                                                  BatchCtl c, int32_t k, uint8_t req,
+                                                  uint8_t forbid) {
     extern __shared__ __align__(16) char lds[];
     const int32_t i = order[blockIdx.x];
-    batch_topk(insts[i], lds, ghist_all + (size_t)i * kSegBins, k, req, forbid);
+    const BatchInst &I = insts[i];
+    const BtState st = c.state[i];
+    if (st.mode == kBtFallback) {
+        batch_topk(I, lds, c.hist0 + (int64_t)i * kSegBins, k, req, forbid);
+        return;
+    }
+    SegLds L;
+    seg_lds_layout(lds, &L);
+    const int tid = threadIdx.x;
+    const int32_t ns = min(st.n_sel, (int32_t)MPS_MAX_BATCH_TOPK);
+    const int32_t nc = min(st.n_cand, (int32_t)kSegCap);
+    const uint64_t *sel = c.sel + (int64_t)i * MPS_MAX_BATCH_TOPK;
+    const uint64_t *cand = c.cand + (int64_t)i * kSegCap;
+    for (int j = tid; j < ns; j += kBT) L.sel[j] = gld(sel + j);
+    for (int j = tid; j < nc; j += kBT) L.cand[0][j] = gld(cand + j);
+    if (tid == 0) {
+        L.cnt[0] = ns;
+        L.cnt[1] = nc;
+        L.cnt[2] = 0;
+        L.cnt[3] = 0;
+    }
+    __syncthreads();
+    int32_t n_sel_final = ns;
+    if (st.mode == kBtCollect0)
+        n_sel_final = refine_chip(L, 0, st.need);
+    else if (st.mode == kBtCollect1)
+        n_sel_final = refine_chip(L, 1, st.need);
+    write_topk(I, L, n_sel_final, k);
 }
 
 hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st) {
-    const int64_t nwords = batch_ctl_words(bl.n_inst);
+    const BatchCtl c = batch_ctl(bl.ctl, bl.n_inst);
+    const int64_t nwords = batch_ctl_clear_words(bl.n_inst);
     int64_t g = (nwords + 255) / 256;
     if (g > 1024) g = 1024;
     hipLaunchKernelGGL(k_batch_init, dim3((unsigned)g), dim3(256), 0, st, bl.ctl, nwords);
-    uint32_t *head = bl.ctl, *ghist = bl.ctl + 2;
     if (bl.n_items1 > 0)
         hipLaunchKernelGGL(k_batch_blocks, dim3((unsigned)bl.grid1), dim3(kBT), bl.lds_bytes, st,
-                           bl.insts, bl.items1, bl.n_items1, head);
+                           bl.insts, bl.items1, bl.n_items1, c.head);
     if (bl.n_items2 > 0)
         hipLaunchKernelGGL(k_batch_moves, dim3((unsigned)bl.grid2), dim3(kBT), bl.lds_bytes, st,
-                           bl.insts, bl.items2, bl.n_items2, head + 1, ghist, bl.req, bl.forbid);
-    hipLaunchKernelGGL(k_batch_topk, dim3((unsigned)bl.n_inst), dim3(kBT), bl.lds_bytes, st,
-                       bl.insts, bl.order, ghist, bl.k, bl.req, bl.forbid);
+                           bl.insts, bl.items2, bl.n_items2, c.head + 1, c.hist0, bl.req,
+                           bl.forbid);
+    const dim3 per_model((unsigned)bl.n_inst);
+    hipLaunchKernelGGL(k_bt_select0, per_model, dim3(kBT), 0, st, c, bl.k);
+    if (bl.n_items2 > 0)
+        hipLaunchKernelGGL(k_bt_pass1, dim3((unsigned)bl.grid2), dim3(kBT), 0, st, bl.insts,
+                           bl.items2, bl.n_items2, bl.claim, c, bl.req, bl.forbid);
+    hipLaunchKernelGGL(k_bt_select1, per_model, dim3(kBT), 0, st, c);
+    if (bl.n_items2 > 0)
+        hipLaunchKernelGGL(k_bt_collect, dim3((unsigned)bl.grid2), dim3(kBT), 0, st, bl.insts,
+                           bl.items2, bl.n_items2, bl.claim, c, bl.req, bl.forbid);
+    hipLaunchKernelGGL(k_bt_final, per_model, dim3(kBT), bl.lds_bytes, st, bl.insts, bl.order, c,
+                       bl.k, bl.req, bl.forbid);
     return hipGetLastError();
 }
 
