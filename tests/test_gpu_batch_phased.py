@@ -163,3 +163,45 @@ def test_phased_rejects_bad_arguments():
     with pytest.raises(MpsError):
         b.set_workgroups(-1)
     b.close()
+
+
+@pytest.mark.parametrize("case", ["all_equal", "narrow", "mixed"])
+def test_phased_topk_selection_paths(case):
+    """The top-k phases take different routes by how the boundary keys
+    spread: all scores equal (more than 1,024 keys share every score bit:
+    the single-workgroup walk), scores in a narrow band (a level-1 pass),
+    and a batch mixing both with an ordinary model.  Every route gives the
+    sort-based selection of the same scores, bit for bit."""
+    from paper_2511_18296_amd.binding import Batch, Model
+    inst = mpsgen.make_instance(16, 14, 6, 40, 8, 2.0, 530)
+    D = inst.T + 1
+    osc, ofl = oracle.Oracle(inst).eval_moves(inst.p0, include_never=True)
+    ok = ((ofl & oracle.PREC_OK) != 0) & ((ofl & (oracle.NOOP | oracle.BAD)) == 0)
+    cand = np.flatnonzero(ok)
+    assert len(cand) > 1000
+    lists = []
+    if case in ("all_equal", "mixed"):
+        i = cand[len(cand) // 2]                      # one qualifying move, repeated
+        lists.append((np.full(6000, i // D, np.int32), np.full(6000, i % D, np.int8)))
+    if case in ("narrow", "mixed"):
+        # the 150 best moves, 40 copies each: 2,280 keys share the top 12 key
+        # bits of the boundary, at most 80 the top 23
+        order = cand[np.argsort(-osc[cand], kind="stable")]
+        sel = np.repeat(order[:150], 40)
+        lists.append(((sel // D).astype(np.int32), (sel % D).astype(np.int8)))
+    if case == "mixed":
+        lists.append(mpsgen.random_moves(inst.N, inst.T, 20000, 532))
+    models = [Model.from_instance(inst) for _ in lists]
+    dev = [(torch.from_numpy(b).cuda(), torch.from_numpy(p).cuda()) for b, p in lists]
+    for k in (256, 1024):
+        b = Batch(models, dev, k)
+        b.run()
+        torch.cuda.synchronize()
+        for i in range(len(lists)):
+            sc, fl = to_np(b.score[i]), to_np(b.flags[i])
+            ri, rs = oracle.topk(sc, fl, k)
+            c = int(b.top_count[i].item())
+            assert c == len(ri), (case, i, k, c, len(ri))
+            np.testing.assert_array_equal(to_np(b.top_idx[i])[:c], ri)
+            np.testing.assert_array_equal(to_np(b.top_score[i])[:c], rs.astype(np.float32))
+        b.close()
