@@ -18,12 +18,12 @@
 // blocks; lane l owns block b0 + l.  The eight waves stream disjoint eighths
 // of the scenario-major v[s][b] (each wave instruction reads 256 contiguous
 // bytes) and then take every eighth destination period.  Every global load of
-// a tile (its rows of v, block data, ore words, tables) is issued before
-// the first wait, so a tile costs one memory round trip.  Scores and flags of
-// the tile are staged in LDS and written as one contiguous, coalesced range.
-// With at most 8 ore words (S <= 256) a lane scores its block's destinations
-// with the block invariants hoisted and each destination's table entries read
-// once per wave (score_block_fast).
+// a tile is issued before the first wait: first the small ones (block data,
+// ore words, tables), then the rows of v.  With at most 8 ore words
+// (S <= 256) everything of a move but its risk term is computed while the
+// rows are still in flight (score_block_pre), and only the risk term waits
+// for c_b (score_block_post).  Scores and flags of the tile are staged in LDS
+// and written as one contiguous, coalesced range.
 #include <float.h>
 
 #include "eval_dev.h"
@@ -43,8 +43,16 @@ __global__ void __launch_bounds__(kNT, KCH <= 25 ? 8 : 1) k_eval_exh(DevModel m,
     extern __shared__ __align__(16) char lds[];
     TileLds L;
     tile_lds_layout(m, lds, &L);
-    float *stage_s = (float *)L.end;
-    uint8_t *stage_f = (uint8_t *)(L.end + a16(sizeof(float) * 64 * D));
+    // the tile's moves in LDS: d(t) - d(p_b), the two penalty changes (the
+    // processing one replaced by the score), flags
+    const size_t sf = a16(sizeof(float) * 64 * D);
+    MoveStage st;
+    st.dpp = (float *)L.end;
+    st.dd = (float *)(L.end + sf);
+    st.dpm = (float *)(L.end + 2 * sf);
+    st.f = (uint8_t *)(L.end + 3 * sf);
+    float *stage_s = st.dpp;
+    uint8_t *stage_f = st.f;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -52,31 +60,35 @@ __global__ void __launch_bounds__(kNT, KCH <= 25 ? 8 : 1) k_eval_exh(DevModel m,
     const int64_t b = b0 + lane;
     const bool valid = b < m.N;
 
-    // one round trip: block data (one wave loads it for the tile; the others
-    // take it from LDS), the wave's rows of v, tables, ore words.  The block
-    // loads go first, so that waiting for them does not wait for the rows.
+    // one round trip.  The small loads go first (block data, which one wave
+    // loads for the tile and the others take from LDS; tables; ore words), so
+    // that waiting for them does not wait for the rows of v.
     BlockInfo bi{};
     if (wave == 0 && valid) bi = load_block(m, b);
+    const TablePrefetch tp = issue_tables<false>(m);
+    uint32_t ow0 = 0;
+    if (valid && wave < m.W) ow0 = m.ore[(int64_t)wave * m.N + b];
+    const float var32 = gld(&m.sc->var32), sig32 = gld(&m.sc->sigma32);
     int32_t s0, s1;
     wave_range(m, wave, s0, s1);
     float x[KCH];
     issue_rows(m, b, valid, s0, s1, x);
-    const TablePrefetch tp = issue_tables(m);
-    uint32_t ow0 = 0;
-    if (valid && wave < m.W) ow0 = m.ore[(int64_t)wave * m.N + b];
-    const float var32 = m.sc->var32, sig32 = m.sc->sigma32;
     if (wave < m.W) L.ore[wave * 64 + lane] = ow0;
     for (int32_t w = wave + kNW; w < m.W; w += kNW)
         L.ore[w * 64 + lane] = valid ? m.ore[(int64_t)w * m.N + b] : 0u;
-    const TabView tv = commit_tables(m, L, tp);   // barrier inside
-    L.cpart[wave * 64 + lane] = wave_dot(m, m.e32, b, valid, s0, s1, x);
+    const TabView tv = commit_tables<false>(m, L, tp);   // barrier inside (LDS only)
     if (wave == 0 && valid) L.bs[lane] = share_block(m, tv, L, lane, bi);
+    __syncthreads();
+    const float lam = (float)m.lambda, pps = (float)(m.pen_proc / m.S);
+    // the block's shared quantities are read from LDS where used
+    const BlockShare &bs = L.bs[lane];
+    // while the rows travel: the moves' flags and penalty changes
+    if (valid && m.W <= 8) score_block_pre(m, L, wave, lane, bs, D, pps, st);
+    L.cpart[wave * 64 + lane] = wave_dot(m, m.e32, b, valid, s0, s1, x);
     __syncthreads();
     const float c = tile_c(L, lane, m.S);
 
-    const float lam = (float)m.lambda, pps = (float)(m.pen_proc / m.S);
     if (valid) {
-        const BlockShare bs = L.bs[lane];
         auto emit = [&](int32_t t, const MoveOut &o) {
             stage_s[lane * D + t] = o.score;
             stage_f[lane * D + t] = o.flags;
@@ -88,7 +100,7 @@ __global__ void __launch_bounds__(kNT, KCH <= 25 ? 8 : 1) k_eval_exh(DevModel m,
             }
         };
         if (m.W <= 8) {
-            score_block_fast(m, tv, L, wave, lane, bs, c, D, var32, sig32, lam, pps, emit);
+            score_block_post(wave, lane, bs, c, D, var32, sig32, lam, st, emit);
         } else {
             auto ow = [&](int32_t w) { return L.ore[w * 64 + lane]; };
             for (int32_t t = wave; t < D; t += kNW)
@@ -178,7 +190,7 @@ hipError_t launch_eval(const DevModel &m, const mps_moves &mv, float *score, uin
     const size_t base = tile_lds_layout(m, nullptr, nullptr);
     if (mv.exhaustive) {
         const int32_t D = mv.include_never ? m.T + 1 : m.T;
-        const size_t lds = base + a16(sizeof(float) * 64 * D) + a16((size_t)64 * D);
+        const size_t lds = base + 3 * a16(sizeof(float) * 64 * D) + a16((size_t)64 * D);
         // rows per wave: up to 16 -> 16, 17..25 -> 25, more -> 32 (and a loop)
         const int32_t rows = (m.S + kNW - 1) / kNW;
         auto go = [&](auto kern) {

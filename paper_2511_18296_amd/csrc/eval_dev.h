@@ -26,6 +26,7 @@ struct TabView {
     const AddEntry *add_l, *add_g;         // list entries: LDS copy / in HBM
     const RemEntry *rem_l, *rem_g;
     bool small;                            // the lists fit their LDS copies
+    bool add_small;                        // ... and the added-tonnage one was made
 };
 
 // Risk, penalty and flag arithmetic of one move, given the block quantities.
@@ -63,7 +64,7 @@ __device__ __forceinline__ MoveOut score_move(const DevModel &m, const TabView &
             }
         };
         // one loop per memory: LDS copy, or the lists in HBM
-        if (tv.small)
+        if (tv.add_small)
             for (int32_t j = j0; j < j1; ++j) entry(tv.add_l[j]);
         else
             for (int32_t j = j0; j < j1; ++j) entry(gld(tv.add_g + j));
@@ -226,6 +227,10 @@ struct TablePrefetch {
     RemEntry re;
 };
 
+// kLists = false leaves the near-capacity list of the added tonnage in HBM
+// (its LDS copy is not made), for kernels that read it with scalar loads; the
+// list of the removed tonnage is always staged.
+template <bool kLists = true>
 __device__ __forceinline__ TablePrefetch issue_tables(const DevModel &m) {
     const int tid = threadIdx.x;
     const int32_t T = m.T, TW = m.T * m.W;
@@ -235,13 +240,14 @@ __device__ __forceinline__ TablePrefetch issue_tables(const DevModel &m) {
     f.fa = tid < TW ? gld(m.tab.full_add + tid) : 0u;
     f.fr = tid < TW ? gld(m.tab.full_rem + tid) : 0u;
     f.rg = tid < 4 * T ? gld(m.tab.rng + tid) : 0;
-    f.ae = gld(m.tab.add_packed + min(tid, kListCap - 1));
+    if (kLists) f.ae = gld(m.tab.add_packed + min(tid, kListCap - 1));
     f.re = gld(m.tab.rem_packed + min(tid, kListCap - 1));
     return f;
 }
 
 // Commit the prefetched tables to LDS (plus any remainder of large tables),
 // then barrier.  Lists longer than kListCap in total are read in place.
+template <bool kLists = true>
 __device__ __forceinline__ TabView commit_tables(const DevModel &m, const TileLds &L,
                                                  const TablePrefetch &f) {
     const int tid = threadIdx.x;
@@ -258,7 +264,7 @@ __device__ __forceinline__ TabView commit_tables(const DevModel &m, const TileLd
         L.fr[i] = gld(m.tab.full_rem + i);
     }
     if (tid < kListCap) {
-        L.al[tid] = f.ae;
+        if (kLists) L.al[tid] = f.ae;
         L.rl[tid] = f.re;
     }
     __syncthreads();
@@ -268,6 +274,7 @@ __device__ __forceinline__ TabView commit_tables(const DevModel &m, const TileLd
     tv.rng = L.rng;
     const bool small = L.rng[2 * T - 1] <= kListCap && L.rng[4 * T - 1] <= kListCap;
     tv.small = small;
+    tv.add_small = kLists && small;
     tv.add_l = L.al;
     tv.add_g = m.tab.add_packed;
     tv.rem_l = L.rl;
@@ -366,20 +373,26 @@ __device__ __forceinline__ BlockShare share_block(const DevModel &m, const TabVi
     return s;
 }
 
+// The moves of one lane's block are scored in two halves around the dot
+// product: everything but the risk term does not depend on c_b, so it runs
+// while the block's v rows are still in flight.  The halves meet in LDS.
+struct MoveStage {
+    float *dd;     // [64][D] d(t) - d(p_b)
+    float *dpp;    // [64][D] processing penalty change; the score replaces it
+    float *dpm;    // [64][D] mining penalty change
+    uint8_t *f;    // [64][D] flags
+};
+
 // Every destination t = wave, wave + kNW, ... of one lane's block, for
-// models with at most 8 ore words (S <= 256).  The block's invariants come
-// shared (share_block) and its ore words sit in registers; each
-// destination's table entries (d(t), M[t], the full-add words, the
-// near-capacity list) are the same for every lane of the wave, so they are
-// read once per wave (scalar loads).  Same definitions as score_move; the
-// risk term uses the hardware square root and reciprocal.  emit(t, out)
-// receives each move.
-template <class Emit>
-__device__ __forceinline__ void score_block_fast(const DevModel &m, const TabView &tv,
-                                                 const TileLds &L, int wave, int lane,
-                                                 const BlockShare &bi, float c, int32_t D,
-                                                 float var32, float sig32, float lam, float pps,
-                                                 Emit emit) {
+// models with at most 8 ore words (S <= 256): the flags and the two penalty
+// changes.  The block's invariants come shared (share_block) and its ore
+// words sit in registers; each destination's table entries (d(t), M[t], the
+// full-add words, the near-capacity list) are the same for every lane of the
+// wave, so they are read once per wave (scalar loads).  Same definitions as
+// score_move.
+__device__ __forceinline__ void score_block_pre(const DevModel &m, const TileLds &L, int wave,
+                                                int lane, const BlockShare &bi, int32_t D,
+                                                float pps, const MoveStage &st) {
     const int32_t T = m.T, W = m.W;
     uint32_t orw[8];
 #pragma unroll
@@ -393,11 +406,6 @@ __device__ __forceinline__ void score_block_fast(const DevModel &m, const TabVie
     for (int32_t t = wave; t < D; t += kNW) {
         const bool noop = t == pb;
         const float dd = (float)(gld(m.d64 + t) - dpb);
-        const float dvar = fmaf(2.0f * dd, c, dd * dd * bi.Vb);
-        const float vp = fmaxf(var32 + dvar, 0.0f);
-        const float den = __builtin_amdgcn_sqrtf(vp) + sig32;
-        const float dsig = den > 0.0f ? dvar * __builtin_amdgcn_rcpf(den) : 0.0f;
-        const float dr = fmaf(dd, bi.mb, -lam * dsig);
         float addv = 0.0f;
         bool viol = false, mine_ok = true;
         double am = am_rem;
@@ -424,14 +432,37 @@ __device__ __forceinline__ void score_block_fast(const DevModel &m, const TabVie
             mine_ok = x <= mcap;
             am += fmin(fmax(x - mcap, 0.0), ton);
         }
-        MoveOut o;
         uint8_t f = 0;
         if (bi.lo <= t && t <= bi.hi) f |= MPS_PREC_OK;
         if (noop || t == T || mine_ok) f |= MPS_MINE_OK;
         if (noop || t == T || !viol) f |= MPS_PROC_OK;
         if (noop) f |= MPS_NOOP;
-        const float dpp = noop ? 0.0f : pps * (addv - remv);
-        const float dpm = noop ? 0.0f : (float)(m.pen_mine * am);
+        const int32_t i = lane * D + t;
+        st.dd[i] = dd;
+        st.dpp[i] = noop ? 0.0f : pps * (addv - remv);
+        st.dpm[i] = noop ? 0.0f : (float)(m.pen_mine * am);
+        st.f[i] = f;
+    }
+}
+
+// The second half, once c_b is known: the risk term (hardware square root and
+// reciprocal) and the score.  emit(t, out) receives each move.
+template <class Emit>
+__device__ __forceinline__ void score_block_post(int wave, int lane, const BlockShare &bi,
+                                                 float c, int32_t D, float var32, float sig32,
+                                                 float lam, const MoveStage &st, Emit emit) {
+    for (int32_t t = wave; t < D; t += kNW) {
+        const int32_t i = lane * D + t;
+        const float dd = st.dd[i];
+        const uint8_t f = st.f[i];
+        const bool noop = (f & MPS_NOOP) != 0;
+        const float dvar = fmaf(2.0f * dd, c, dd * dd * bi.Vb);
+        const float vp = fmaxf(var32 + dvar, 0.0f);
+        const float den = __builtin_amdgcn_sqrtf(vp) + sig32;
+        const float dsig = den > 0.0f ? dvar * __builtin_amdgcn_rcpf(den) : 0.0f;
+        const float dr = fmaf(dd, bi.mb, -lam * dsig);
+        const float dpp = st.dpp[i], dpm = st.dpm[i];
+        MoveOut o;
         o.flags = f;
         o.dr = noop ? 0.0f : dr;
         o.dpp = dpp;
