@@ -199,3 +199,26 @@ def test_repair_rejects_too_many_scenarios():
     cnt = torch.tensor([4], dtype=torch.int32, device="cuda")
     with pytest.raises(MpsError):
         m.repair(MoveSet(), idx, cnt)
+
+
+
+@pytest.mark.parametrize("S,T,hard", [(256, 6, False), (257, 5, True), (1024, 4, False)])
+def test_repair_scenario_chunk_edges(S, T, hard):
+    """S at the edges of the walk's register chunks of 256 scenarios (one
+    whole chunk, one scenario into the second, the largest S supported):
+    same accept decisions, schedule and objective as the oracle walk."""
+    from paper_2511_18296_amd.binding import MoveSet, TopK
+    inst = mpsgen.make_instance(9, 8, 4, S, T, 2.0, 540 + S)
+    m = gpu_model(inst)
+    sc, fl = m.eval_moves()
+    k = 300
+    t = TopK(sc.numel(), k)
+    idx, _, cnt = t(sc, fl)
+    cand = to_np(idx)[:int(cnt.item())]
+    D = inst.T + 1
+    applied = m.repair(MoveSet(), idx, cnt, hard=hard)
+    o = oracle.Oracle(inst)
+    q, a, J, _ = o.repair(inst.p0, cand // D, (cand % D).astype(np.int8), hard=hard)
+    assert int(applied.item()) == a
+    np.testing.assert_array_equal(to_np(m.get_schedule()), q)
+    assert m.objective()["J"] == pytest.approx(o.objective(q)["J"], rel=1e-11)
