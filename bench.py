@@ -153,6 +153,74 @@ def batched_leg(steps, k=256):
 RELAX = (100.0 / (2 * 15600), 100.0 / (2 * 15600), 100.0 * 15600)
 
 
+def burst_seconds(fn, n=20):
+    """Seconds per call of fn(i), over n back-to-back calls between two HIP
+    events on the current stream (after one untimed call)."""
+    import torch
+    fn(0)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(n):
+        fn(i)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / n * 1e-3
+
+
+def copy_peak_gbs(mib=256):
+    """Device-to-device copy bandwidth (read + write bytes) of two rotating
+    pairs of MIB MiB buffers."""
+    import torch
+    n = mib * (1 << 20) // 4
+    bufs = [torch.ones(n, dtype=torch.float32, device="cuda") for _ in range(4)]
+    t = burst_seconds(lambda i: bufs[2 * (i % 2) + 1].copy_(bufs[2 * (i % 2)]), 10)
+    del bufs
+    return 2 * n * 4 / t / 1e9
+
+
+def kernel_legs(models, inst):
+    """The other rows of the path on their own, each timed over a burst of
+    back-to-back launches rotating over the copies of the 54,000-block
+    instance: the relaxed forward and adjoint, the gradient ranking; and the
+    list evaluation of the paper-scale configuration (32,000 blocks, S = 50,
+    250,000 random moves), a latency-sized case."""
+    import torch
+    import mpsgen
+    from paper_2511_18296_amd.binding import Model, MoveSet
+    N, S, T = inst.N, inst.S, inst.T
+    W = (S + 31) // 32
+    x = torch.from_numpy(mpsgen.integer_x(inst.p0, T)).cuda()
+    saved = [m.relaxed_saved() for m in models]
+    J = [torch.empty(6, dtype=torch.float64, device="cuda") for _ in models]
+    grads = [torch.empty_like(x) for _ in models]
+    nm = len(models)
+    t_fwd = burst_seconds(lambda i: models[i % nm].relaxed_fwd(x, RELAX, saved[i % nm], J[i % nm]))
+    t_bwd = burst_seconds(
+        lambda i: models[i % nm].relaxed_bwd(x, RELAX, saved[i % nm], None, grads[i % nm]))
+    t_rank = burst_seconds(lambda i: models[i % nm].rank_moves(grads[i % nm], 4096))
+    b_fwd = 4 * S * N + 4 * W * N + 4 * N * T
+    b_bwd = 4 * S * N + 4 * W * N + 8 * N * T
+    out = {
+        "relaxed_fwd": {"us": t_fwd * 1e6, "algorithmic_bytes": b_fwd,
+                        "GBs": b_fwd / t_fwd / 1e9, "frac": b_fwd / t_fwd / 1e9 / HBM_PEAK_GBS},
+        "relaxed_bwd": {"us": t_bwd * 1e6, "algorithmic_bytes": b_bwd,
+                        "GBs": b_bwd / t_bwd / 1e9, "frac": b_bwd / t_bwd / 1e9 / HBM_PEAK_GBS},
+        "rank_moves_top4096_us": t_rank * 1e6,
+    }
+    pinst = mpsgen.paper_scale()
+    pm = Model.from_instance(pinst)
+    blk, per = mpsgen.random_moves(pinst.N, pinst.T, 250000, 2 + 1000)
+    mv = MoveSet(False, True, torch.from_numpy(blk).cuda(), torch.from_numpy(per).cuda())
+    sc = torch.empty(250000, dtype=torch.float32, device="cuda")
+    fl = torch.empty(250000, dtype=torch.uint8, device="cuda")
+    t_list = burst_seconds(lambda i: pm.eval_moves(mv, out=[sc, fl]))
+    out["list_eval_paper_scale"] = {"us": t_list * 1e6, "moves": 250000,
+                                    "move_scenario_evals_per_s": 250000 * pinst.S / t_list}
+    return out
+
+
 def search_leg(model, seed_state, k):
     """Gradient-ranked search vs exhaustive search from the same seeded schedule."""
     import torch
@@ -273,6 +341,10 @@ def main():
     t_eval_kernel = ea.elapsed_time(eb) / burst * 1e-3
     achieved = B / t_eval_kernel / 1e9
     objs = [m.objective() for m in models]
+    n_applied = [int(a) for a in applied.cpu().tolist()]
+    copy_gbs = copy_peak_gbs()
+    legs = kernel_legs(models, inst)
+    log(f"legs: {json.dumps(legs)}")
     log(f"restore {t_rest*1e6:.1f} us, eval {t_eval*1e6:.1f} us, topk {t_topk*1e6:.1f} us, "
         f"repair {t_rep*1e6:.1f} us, "
         f"step {ms:.3f} ms; eval kernel {t_eval_kernel*1e6:.1f} us in a burst of {burst}")
@@ -301,10 +373,15 @@ def main():
                      "traffic": MEASURED_TRAFFIC.get(eval_source_sha()),
                      "bytes_per_launch": B, "launch_us": t_eval_kernel * 1e6,
                      "timing": f"{burst} back-to-back launches between two HIP events",
+                     "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
                      "source_sha1": eval_source_sha()},
         "phases_us": {"restore": t_rest * 1e6, "eval": t_eval * 1e6, "topk": t_topk * 1e6,
                       "repair": t_rep * 1e6},
-        "eval_move_scenario_evals_per_s": M * S / t_eval,
+        "eval_move_scenario_evals_per_s": M * S / t_eval_kernel,
+        "repair": {"applied_per_step": n_applied[0],
+                   "us_per_applied_move": t_rep * 1e6 / max(1, n_applied[0]),
+                   "us_per_candidate": t_rep * 1e6 / args.k},
+        "legs": legs,
         "final_J": [o["J"] for o in objs],
     }
     if not args.no_search:
