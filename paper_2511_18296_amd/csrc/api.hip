@@ -370,6 +370,8 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     if ((st = chk(launch_block_stats(d, mb32, Vb32, mb64, Vb64, hs), "block statistics")) !=
         MPS_OK)
         return st;
+    if ((st = chk(launch_relaxed_init(d, m->relax_ws, hs), "relaxed stencil")) != MPS_OK)
+        return st;
     // initial schedule: everything in period 0
     std::vector<int8_t> zero((size_t)N, 0);
     if ((st = chk(hipMemcpyAsync(p, zero.data(), N, hipMemcpyHostToDevice, hs), "schedule")) !=
@@ -575,7 +577,7 @@ mps_status mps_relaxed_bwd(mps_model *m, const float *x, const mps_relax_params 
     if (st != MPS_OK) return st;
     if (!x || !saved || !grad_x) return fail(MPS_E_INVALID_ARG, "x, saved and grad_x are required");
     DeviceGuard g(m->device);
-    hipError_t e = launch_relaxed_bwd(m->d, x, *rp, saved, dJ, grad_x, (hipStream_t)stream);
+    hipError_t e = launch_relaxed_bwd(m->d, x, *rp, saved, dJ, grad_x, m->relax_ws, (hipStream_t)stream);
     return e == hipSuccess ? MPS_OK : dev_fail(e, "relaxed backward");
 }
 
@@ -668,7 +670,7 @@ mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_par
     auto round_gradient = [&]() -> hipError_t {
         hipError_t e = launch_integer_x(d, x, hs);
         if (e == hipSuccess) e = launch_relaxed_fwd(d, x, *rp, nullptr, saved, m->relax_ws, hs);
-        if (e == hipSuccess) e = launch_relaxed_bwd(d, x, *rp, saved, nullptr, grad, hs);
+        if (e == hipSuccess) e = launch_relaxed_bwd(d, x, *rp, saved, nullptr, grad, m->relax_ws, hs);
         if (e == hipSuccess) e = launch_rank(d, grad, k, rblk, rper, gain, cnt + 2, rws, hs);
         if (e == hipSuccess) e = launch_eval(d, lst, lscore, lflags, nullptr, nullptr, nullptr, hs);
         if (e == hipSuccess)

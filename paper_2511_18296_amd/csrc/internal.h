@@ -106,7 +106,10 @@ size_t relaxed_ws_bytes(const DevModel &m);
 hipError_t launch_relaxed_fwd(const DevModel &m, const float *x, const mps_relax_params &rp,
                               double *J_out, void *saved, void *ws, hipStream_t st);
 hipError_t launch_relaxed_bwd(const DevModel &m, const float *x, const mps_relax_params &rp,
-                              const void *saved, const double *dJ, float *grad, hipStream_t st);
+                              const void *saved, const double *dJ, float *grad, void *ws,
+                              hipStream_t st);
+// Once per model: the precedence-stencil bits kept in the relaxed workspace.
+hipError_t launch_relaxed_init(const DevModel &m, void *ws, hipStream_t st);
 size_t rank_ws_bytes(const DevModel &m, int32_t k);
 hipError_t launch_rank(const DevModel &m, const float *grad, int32_t k, int32_t *blk,
                        int8_t *per, float *gain_out, int32_t *count, void *ws, hipStream_t st);

@@ -33,6 +33,14 @@ def instance(name):
     if name == "wider":
         # S in (512, 1024], not a multiple of 4
         return mpsgen.make_instance(8, 8, 4, 701, 5, 2.0, 82)
+    if name == "deep":
+        # T = 40 (three period tiles), S + 1 rows in two scenario groups of the
+        # relaxed forward, four scenario passes of its adjoint
+        return mpsgen.make_instance(20, 15, 6, 400, 40, 2.0, 84)
+    if name == "tall":
+        # T = 120: 32-block pieces, three per chunk in the relaxed forward;
+        # 64-block adjoint tiles with five scenario passes
+        return mpsgen.make_instance(25, 20, 20, 150, 120, 2.0, 85)
     if name == "tight":
         inst = mpsgen.make_instance(12, 10, 6, 96, 8, 2.0, 80)
         inst.pcap *= 0.85        # capacities bind in most periods
