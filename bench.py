@@ -41,15 +41,28 @@ MEASURED_TRAFFIC = {
     "bba0b51e32904ab1c461c7f031b504652416cd29": 28083.3 * 1024 * 2.000 + 5537.1 * 1024 * 1.000,
 }
 EVAL_SOURCES = ("eval.hip", "eval_dev.h", "internal.h")
+RELAX_SOURCES = ("relaxed.hip", "internal.h")
+# HBM bytes per call of the relaxed passes on the same instance, from the same
+# counter runs and calibration (profiles/relaxed_fwd_bwd_60x60x15_S200_T20.md):
+# forward = chunk + reduce + final kernels, adjoint = tile kernel.
+MEASURED_RELAX_TRAFFIC = {
+    "3fabbf3acc065d5627638e41167dc14d83bee655": {"relaxed_fwd": (28413.3 + 4028.5 + 9.5) * 1024 * 2.000
+                                 + (4000.6 + 226.5 + 4.7) * 1024 * 1.000,
+                   "relaxed_bwd": 31634.2 * 1024 * 2.000 + 4218.8 * 1024 * 1.000},
+}
 
 
-def eval_source_sha():
+def source_sha(files):
     import hashlib
     h = hashlib.sha1()
-    for f in EVAL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2511_18296_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def eval_source_sha():
+    return source_sha(EVAL_SOURCES)
 
 
 def log(*a):
@@ -202,11 +215,14 @@ def kernel_legs(models, inst):
     t_rank = burst_seconds(lambda i: models[i % nm].rank_moves(grads[i % nm], 4096))
     b_fwd = 4 * S * N + 4 * W * N + 4 * N * T
     b_bwd = 4 * S * N + 4 * W * N + 8 * N * T
+    traffic = MEASURED_RELAX_TRAFFIC.get(source_sha(RELAX_SOURCES), {})
     out = {
         "relaxed_fwd": {"us": t_fwd * 1e6, "algorithmic_bytes": b_fwd,
-                        "GBs": b_fwd / t_fwd / 1e9, "frac": b_fwd / t_fwd / 1e9 / HBM_PEAK_GBS},
+                        "GBs": b_fwd / t_fwd / 1e9, "frac": b_fwd / t_fwd / 1e9 / HBM_PEAK_GBS,
+                        "traffic": traffic.get("relaxed_fwd")},
         "relaxed_bwd": {"us": t_bwd * 1e6, "algorithmic_bytes": b_bwd,
-                        "GBs": b_bwd / t_bwd / 1e9, "frac": b_bwd / t_bwd / 1e9 / HBM_PEAK_GBS},
+                        "GBs": b_bwd / t_bwd / 1e9, "frac": b_bwd / t_bwd / 1e9 / HBM_PEAK_GBS,
+                        "traffic": traffic.get("relaxed_bwd")},
         "rank_moves_top4096_us": t_rank * 1e6,
     }
     pinst = mpsgen.paper_scale()
