@@ -455,7 +455,8 @@ __global__ void __launch_bounds__(kThreads) k_repair_walk(DevModel m, int32_t n_
     struct Cand {
         uint32_t nb;     // this lane's neighbour word
         float4 v[NQ];    // v column, this lane's scenarios
-        uint32_t ow[NQ]; // their ore bits
+        uint32_t ow[NQ]; // their ore bits (the whole word until the window
+                         // start shifts this lane's four to the bottom)
         double mb, Vb, ton;
     };
     auto load_rec = [&](size_t bo, int32_t i, Cand &c) {
@@ -472,7 +473,7 @@ __global__ void __launch_bounds__(kThreads) k_repair_walk(DevModel m, int32_t n_
             const int32_t s0 = 256 * q + 4 * lane;
             if (s0 < S) {
                 c.v[q] = *(const float4 *)(vb + s0);
-                c.ow[q] = ob[s0 >> 5] >> (s0 & 31);
+                c.ow[q] = ob[s0 >> 5];   // shifted at use: no wait here
             } else {
                 c.v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
                 c.ow[q] = 0;
@@ -498,6 +499,8 @@ __global__ void __launch_bounds__(kThreads) k_repair_walk(DevModel m, int32_t n_
             const int32_t t = valid ? (int32_t)(nb0 >> kNbTShift) : 0;
             const int32_t p0 = valid ? (int32_t)((nb0 >> 16) & 0xffu) : 0;
             const uint32_t slot0 = (nb0 & 0xffffu) - 1;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) C.ow[q] >>= (4 * lane) & 31;
             double ot[NQ][4], op[NQ][4];
             double mlt = 0.0, mlp = 0.0, dd = 0.0;
             uint32_t cur = 0;
@@ -531,9 +534,6 @@ __global__ void __launch_bounds__(kThreads) k_repair_walk(DevModel m, int32_t n_
                 const uint32_t sl = C.nb & 0xffffu;
                 cur = sl ? (uint32_t)pmap[sl - 1] : (C.nb >> 16) & 0xffu;
             }
-            // the next window's record (same batch) travels meanwhile; with
-            // more than two chunks there are not registers enough for that
-            if (kPrefetch && pos + kWaves + wave < c1) load_rec(bo, pos + kWaves + wave - c0, N);
             // v and the ore bits as doubles, for the whole window
             double vd[NQ][4], inb[NQ][4];
             if constexpr (kRich) {
@@ -546,6 +546,15 @@ __global__ void __launch_bounds__(kThreads) k_repair_walk(DevModel m, int32_t n_
                         inb[q][j] = ((C.ow[q] >> j) & 1u) ? 1.0 : 0.0;
                     }
                 }
+            }
+            // the next window's record (same batch) travels meanwhile; with
+            // more than two chunks there are not registers enough for that.
+            // The LDS reads of this window are waited for first (free after
+            // the state rows' wait), so that no later wait for this window's
+            // record also waits for these reads.
+            if constexpr (kPrefetch) {
+                __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+                if (pos + kWaves + wave < c1) load_rec(bo, pos + kWaves + wave - c0, N);
             }
             // ---- step 2, as long as some candidate of the window is open
             while (true) {
@@ -634,23 +643,28 @@ __global__ void __launch_bounds__(kThreads) k_repair_walk(DevModel m, int32_t n_
                 const CandHdr &er = *(const CandHdr *)rr;
                 const float *vr = (const float *)(rr + sizeof(CandHdr));
                 const uint32_t *orr = (const uint32_t *)(vr + Sp);
-                const uint32_t wnb0 = er.nb[0];
-                const double w_ton = er.ton;
-                const double ddr = res[3 * r + 2];
-                mu = res[3 * r];
-                var = res[3 * r + 1];
+                // every read of the applied candidate in one LDS trip: the
+                // column reads are unconditional (lanes past S read the
+                // record's first entries) and their values masked after
                 float4 wv[NQ];
                 uint32_t wo[NQ];
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     const int32_t s0 = 256 * q + 4 * lane;
-                    if (s0 < S) {
-                        wv[q] = *(const float4 *)(vr + s0);
-                        wo[q] = orr[s0 >> 5] >> (s0 & 31);
-                    } else {
-                        wv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-                        wo[q] = 0;
-                    }
+                    const int32_t sc = s0 < S ? s0 : 0;
+                    wv[q] = *(const float4 *)(vr + sc);
+                    wo[q] = orr[sc >> 5];
+                }
+                const uint32_t wnb0 = er.nb[0];
+                const double w_ton = er.ton;
+                const double ddr = res[3 * r + 2];
+                mu = res[3 * r];
+                var = res[3 * r + 1];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int32_t s0 = 256 * q + 4 * lane;
+                    if (s0 >= S) wv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    wo[q] = s0 < S ? wo[q] >> (s0 & 31) : 0u;
                 }
                 const int32_t w_t = (int32_t)(wnb0 >> kNbTShift);
                 const int32_t w_p0 = (int32_t)((wnb0 >> 16) & 0xffu);
