@@ -168,7 +168,12 @@ mps_status mps_state_restore(mps_model *m, const void *buf, void *stream);
  *   d_risk, d_pen_proc, d_pen_mine  float [n_moves] or NULL: the change of
  *          mu - lambda*sigma and of the two penalty terms (score =
  *          d_risk - d_pen_proc - d_pen_mine).
- * n_moves = N*D (exhaustive) or moves->n.  Output index = move index. */
+ * n_moves = N*D (exhaustive) or moves->n.  Output index = move index.
+ * One 64-block tile's period tables stay on chip, so S and T together are
+ * bounded by the LDS of a workgroup: about 12.6 KB + 864*T + 256*W + 8*T*W
+ * bytes with W = ceil(S/32) (exhaustive; a little less for lists).  On a
+ * 160 KB device that allows S = 4096 with T <= 62, or T = 126 with
+ * S <= 1056.  Beyond it: MPS_E_INVALID_ARG, before any device work. */
 mps_status mps_eval_moves(mps_model *m, const mps_moves *moves, float *score,
                           uint8_t *flags, float *d_risk, float *d_pen_proc,
                           float *d_pen_mine, void *stream);
@@ -260,7 +265,9 @@ mps_status mps_rank_moves(mps_model *m, const float *grad_x, int32_t k, int32_t 
  *     moves, evaluate the top k exactly, top k, repair }; when a round applies
  *     nothing, one exhaustive round certifies (and the loop continues if it
  *     applied something).
- * ALLOCATES its buffers and SYNCHRONISES every round (not capturable). */
+ * ALLOCATES its buffers and SYNCHRONISES every round (not capturable).
+ * S <= MPS_MAX_REPAIR_SCENARIOS, and S and T must fit the LDS bound of
+ * mps_eval_moves; otherwise MPS_E_INVALID_ARG before any device work. */
 typedef struct {
     int64_t iterations;    /* rounds run */
     int64_t evaluations;   /* moves evaluated exactly (eval calls) */

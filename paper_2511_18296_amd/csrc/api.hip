@@ -463,6 +463,18 @@ static mps_status check_moves(const mps_model *m, const mps_moves *mv) {
     return MPS_OK;
 }
 
+// The evaluation kernels keep one tile's tables in LDS: S and T together must
+// leave them room.
+static mps_status check_eval_lds(const mps_model *m, const mps_moves &mv) {
+    const size_t need = eval_lds_bytes(m->d, mv);
+    if (need > (size_t)m->max_lds)
+        return fail(MPS_E_INVALID_ARG,
+                    "evaluating moves of this model needs %zu bytes of LDS (T = %d periods of "
+                    "%d ore words per tile), device allows %d: reduce S or T",
+                    need, m->d.T, m->d.W, m->max_lds);
+    return MPS_OK;
+}
+
 mps_status mps_eval_moves(mps_model *m, const mps_moves *moves, float *score, uint8_t *flags,
                           float *d_risk, float *d_pen_proc, float *d_pen_mine, void *stream) {
     if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
@@ -473,6 +485,7 @@ mps_status mps_eval_moves(mps_model *m, const mps_moves *moves, float *score, ui
                           : moves->n;
     if (n_moves == 0) return MPS_OK;
     if (!score || !flags) return fail(MPS_E_INVALID_ARG, "score and flags are required");
+    if ((st = check_eval_lds(m, *moves)) != MPS_OK) return st;
     int nc = (d_risk != nullptr) + (d_pen_proc != nullptr) + (d_pen_mine != nullptr);
     if (nc != 0 && nc != 3)
         return fail(MPS_E_INVALID_ARG, "component outputs must be all given or all NULL");
@@ -624,6 +637,12 @@ mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_par
         return fail(MPS_E_INVALID_ARG, "repair supports S <= %d (got %d)", kRepairMaxScen, d.S);
     if (repair_lds_bytes(d, k) > (size_t)m->max_lds)
         return fail(MPS_E_INVALID_ARG, "repair state does not fit in LDS");
+    {
+        mps_moves all{};
+        all.exhaustive = 1;
+        all.include_never = 1;
+        if ((st = check_eval_lds(m, all)) != MPS_OK) return st;
+    }
     DeviceGuard g(m->device);
     SearchBufs B;
     float *score = B.get<float>(nm);

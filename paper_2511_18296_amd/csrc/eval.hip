@@ -183,6 +183,13 @@ __global__ void __launch_bounds__(kNT) k_eval_list(DevModel m, int64_t n, const 
     }
 }
 
+size_t eval_lds_bytes(const DevModel &m, const mps_moves &mv) {
+    const size_t base = tile_lds_layout(m, nullptr, nullptr);
+    if (!mv.exhaustive) return base;
+    const int32_t D = mv.include_never ? m.T + 1 : m.T;
+    return base + 3 * a16(sizeof(float) * 64 * D) + a16((size_t)64 * D);
+}
+
 hipError_t launch_eval(const DevModel &m, const mps_moves &mv, float *score, uint8_t *flags,
                        float *dR, float *dPp, float *dPm, hipStream_t st) {
     const bool comp = dR != nullptr;
@@ -190,7 +197,7 @@ hipError_t launch_eval(const DevModel &m, const mps_moves &mv, float *score, uin
     const size_t base = tile_lds_layout(m, nullptr, nullptr);
     if (mv.exhaustive) {
         const int32_t D = mv.include_never ? m.T + 1 : m.T;
-        const size_t lds = base + 3 * a16(sizeof(float) * 64 * D) + a16((size_t)64 * D);
+        const size_t lds = eval_lds_bytes(m, mv);
         // rows per wave: up to 16 -> 16, 17..25 -> 25, more -> 32 (and a loop)
         const int32_t rows = (m.S + kNW - 1) / kNW;
         auto go = [&](auto kern) {

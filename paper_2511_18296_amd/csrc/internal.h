@@ -92,6 +92,10 @@ hipError_t launch_set_schedule(const DevModel &m, const int8_t *p_in,
                                double *partial, int chunks, hipStream_t st);
 hipError_t launch_prep(const DevModel &m, hipStream_t st);
 hipError_t launch_objective_copy(const DevModel &m, double *out, hipStream_t st);
+// LDS bytes per workgroup of the evaluation kernels for these moves: the
+// period bit tables and block data of one 64-block tile, plus the per-move
+// staging of the exhaustive form.
+size_t eval_lds_bytes(const DevModel &m, const mps_moves &mv);
 hipError_t launch_eval(const DevModel &m, const mps_moves &mv, float *score,
                        uint8_t *flags, float *dR, float *dPp, float *dPm,
                        hipStream_t st);

@@ -41,6 +41,16 @@ def instance(name):
         # T = 120: 32-block pieces, three per chunk in the relaxed forward;
         # 64-block adjoint tiles with five scenario passes
         return mpsgen.make_instance(25, 20, 20, 150, 120, 2.0, 85)
+    if name == "one_period":
+        # T = 1: the only destinations are period 0 and "never"
+        return mpsgen.make_instance(9, 7, 4, 50, 1, 2.0, 86)
+    if name == "max_periods":
+        # T = MPS_MAX_PERIODS = 126: the widest period range a period byte holds
+        return mpsgen.make_instance(6, 5, 4, 37, 126, 2.0, 87)
+    if name == "max_scen":
+        # S = MPS_MAX_SCENARIOS = 4096 (128 ore words per block; beyond what
+        # the repair walk takes)
+        return mpsgen.make_instance(4, 4, 3, 4096, 8, 2.0, 88)
     if name == "tight":
         inst = mpsgen.make_instance(12, 10, 6, 96, 8, 2.0, 80)
         inst.pcap *= 0.85        # capacities bind in most periods

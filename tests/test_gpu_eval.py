@@ -24,7 +24,8 @@ def test_objective_parity(name):
     assert g["n_prec_viol"] == o["n_prec_viol"] == 0
 
 
-@pytest.mark.parametrize("name", ["tiny", "ragged", "flat", "single", "tight"])
+@pytest.mark.parametrize("name", ["tiny", "ragged", "flat", "single", "tight", "one_period",
+                                  "max_periods", "max_scen"])
 @pytest.mark.parametrize("never", [False, True])
 def test_eval_exhaustive_small(name, never):
     inst = instance(name)
@@ -100,3 +101,16 @@ def test_eval_after_schedule_change_and_determinism():
     compare_scores(to_np(a[0]), osc, ofl, o.objective(p)["mu"], "random schedule")
     g = m.objective()
     assert g["n_prec_viol"] == o.objective(p)["n_prec_viol"]
+
+
+def test_eval_rejects_tables_beyond_lds():
+    """S = 4096 with T = 126 leaves one tile's period tables no room in LDS:
+    an argument error before any launch, and the model stays usable."""
+    from paper_2511_18296_amd.binding import MoveSet, MpsError
+    inst = mpsgen.make_instance(2, 2, 2, 4096, 126, 2.0, 89)
+    m = gpu_model(inst)
+    for ms in (MoveSet(True, True), MoveSet(True, False)):
+        with pytest.raises(MpsError, match="LDS"):
+            m.eval_moves(ms)
+    o = oracle.Oracle(inst).objective(inst.p0)
+    assert m.objective()["J"] == pytest.approx(o["J"], rel=1e-12, abs=1e-6)

@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 RELAX = (100.0 / (2 * 15600), 100.0 / (2 * 15600), 100.0 * 15600)
 
 
-@pytest.mark.parametrize("name", ["tiny", "ragged", "flat", "wider", "deep", "tall", "largest"])
+@pytest.mark.parametrize("name", ["tiny", "ragged", "flat", "single", "one_period", "wider",
+                                  "deep", "tall", "max_periods", "max_scen", "largest"])
 def test_relaxed_forward_and_gradient_against_oracle(name):
     inst = instance(name)
     m = gpu_model(inst)

@@ -86,6 +86,8 @@ def test_topk_on_largest_moves_against_oracle_scores():
                                          ("tight", 1000, False), ("ragged", 200, True),
                                          ("single", 150, False), ("flat", 300, False),
                                          ("wide", 600, False), ("wider", 500, True),
+                                         ("one_period", 300, False),
+                                         ("max_periods", 2000, True),
                                          ("largest", 4096, False)])
 def test_repair_matches_oracle(name, k, hard):
     """Same ordered candidate list on both sides -> same accept decisions,
