@@ -108,8 +108,9 @@ def test_rank_moves_against_oracle_ranking():
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-def test_search_reaches_oracle_quality(mode):
-    inst = instance("tight")
+@pytest.mark.parametrize("name", ["tight", "one_period", "max_periods"])
+def test_search_reaches_oracle_quality(name, mode):
+    inst = instance(name)
     m = gpu_model(inst)
     st = m.search(mode, 256, RELAX)
     o = oracle.Oracle(inst)
@@ -122,7 +123,9 @@ def test_search_reaches_oracle_quality(mode):
     sc, fl = o.eval_moves(p, include_never=True)
     ok = ((fl & oracle.PREC_OK) != 0) & ((fl & oracle.NOOP) == 0)
     assert sc[ok].max() <= 1e-6 * abs(obj["mu"])
-    rel = abs(st["J"] - J_o) / abs(J_o)
-    print(f"mode {mode}: GPU J {st['J']:.8g} vs oracle {J_o:.8g} (rel {rel:.2g}), "
+    # J can sit near zero when the penalties offset the NPV: measure the gap
+    # on the scale of the larger of |J| and |mu|
+    rel = abs(st["J"] - J_o) / max(abs(J_o), abs(obj["mu"]))
+    print(f"{name} mode {mode}: GPU J {st['J']:.8g} vs oracle {J_o:.8g} (rel {rel:.2g}), "
           f"{st['iterations']} rounds, {st['evaluations']} evaluations")
     assert rel <= 1e-3
