@@ -33,11 +33,13 @@ def test_relaxed_forward_and_gradient_against_oracle(name):
           f"of {np.abs(g_o).max():.3g}")
 
 
-def test_gradient_against_fp64_central_differences():
-    """200 random coordinates of a random monotone x on the 54,000-block
-    instance: GPU adjoint vs FP64 central differences (h = 1e-6) of the oracle.
-    Each coordinate costs two full oracle passes; every coordinate is also
-    checked against the oracle's own gradient in the parity test above."""
+FD_COORDS, FD_PARTS = 1000, 5
+
+
+@pytest.fixture(scope="module")
+def fd_case():
+    """The GPU adjoint at a random monotone x on the 54,000-block instance,
+    and 1,000 seeded coordinates to check it at."""
     inst = instance("largest")
     m = gpu_model(inst)
     x = mpsgen.random_monotone_x(inst.N, inst.T, 2005)
@@ -45,14 +47,24 @@ def test_gradient_against_fp64_central_differences():
     saved = m.relaxed_saved()
     m.relaxed_fwd(xt, RELAX, saved)
     g = to_np(m.relaxed_bwd(xt, RELAX, saved))
-    o = oracle.Oracle(inst)
-    xd = x.astype(np.float64)
     rng = np.random.default_rng(3005)
+    coords = [(int(rng.integers(inst.N)), int(rng.integers(inst.T))) for _ in range(FD_COORDS)]
+    return inst, x.astype(np.float64), g, coords
+
+
+@pytest.mark.parametrize("part", range(FD_PARTS))
+def test_gradient_against_fp64_central_differences(fd_case, part):
+    """GPU adjoint vs FP64 central differences (h = 1e-6) of the oracle on
+    1,000 random coordinates, in five parts of 200: each coordinate costs two
+    full oracle passes over 54,000 blocks."""
+    inst, x, g, coords = fd_case
+    o = oracle.Oracle(inst)
+    xd = x.copy()
     h = 1e-6
     gmax = np.abs(g).max()
     worst = 0.0
-    for _ in range(200):
-        b, t = int(rng.integers(inst.N)), int(rng.integers(inst.T))
+    n = FD_COORDS // FD_PARTS
+    for b, t in coords[part * n:(part + 1) * n]:
         old = xd[b, t]
         xd[b, t] = old + h
         jp = o.relaxed(xd, *RELAX, grad=False)
@@ -62,7 +74,7 @@ def test_gradient_against_fp64_central_differences():
         fd = (jp - jm) / (2 * h)
         worst = max(worst, abs(fd - g[b, t]) / gmax)
     assert worst <= 1e-4, worst
-    print(f"max |adjoint - FD| / max|grad| over 200 coordinates: {worst:.3g}")
+    print(f"part {part}: max |adjoint - FD| / max|grad| over {n} coordinates: {worst:.3g}")
 
 
 def test_relaxed_integer_point_equals_objective():
