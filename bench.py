@@ -272,7 +272,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the engine runs on a single MI355X; see DESIGN.md for sharding)",
+              "(the engine runs on a single MI355X; multi-GPU sharding is not built)",
               file=sys.stderr)
         sys.exit(2)
 
