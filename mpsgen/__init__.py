@@ -205,3 +205,94 @@ def batched_specs(n_inst=64, seed=4):
         specs.append(dict(nx=side, ny=side, nz=depth, S=S, T=T, r=r, M=M,
                           seed=400 + i))
     return specs
+
+
+def batch_member(spec):
+    """One instance of the batched workload and its random move list
+    (seed + 1000), from a spec as batched_specs() returns."""
+    inst = make_instance(spec["nx"], spec["ny"], spec["nz"], spec["S"], spec["T"],
+                         spec["r"], spec["seed"])
+    blk, per = random_moves(inst.N, inst.T, spec["M"], spec["seed"] + 1000)
+    return inst, (blk, per)
+
+
+def batch_members(specs, workers=16):
+    """batch_member of every spec, generated in a pool of worker processes."""
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(workers, os.cpu_count() or 1, len(specs)))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(batch_member, specs))
+
+
+def cone_precedence(nx, ny, nz, reach=1):
+    """Explicit predecessor lists of a square slope cone: the predecessors of
+    block (x, y, z) are the blocks (x + dx, y + dy, z - 1) with |dx|, |dy| <=
+    reach inside the grid (reach 1: the 1-9 pattern).  Returns (pred_ptr
+    int32 [N+1], pred_idx int32), each list in increasing block index."""
+    N = nx * ny * nz
+    ptr = np.zeros(N + 1, dtype=np.int32)
+    idx = []
+    for b in range(N):
+        x, y, z = b % nx, (b // nx) % ny, b // (nx * ny)
+        lst = []
+        if z > 0:
+            for dy in range(-reach, reach + 1):
+                for dx in range(-reach, reach + 1):
+                    xa, ya = x + dx, y + dy
+                    if 0 <= xa < nx and 0 <= ya < ny:
+                        lst.append(xa + nx * (ya + ny * (z - 1)))
+        lst.sort()
+        idx.extend(lst)
+        ptr[b + 1] = len(idx)
+    return ptr, np.asarray(idx, dtype=np.int32)
+
+
+def stencil_precedence(nx, ny, nz):
+    """The 1-5 slope stencil written out as explicit predecessor lists (the
+    block right above and its four face neighbours, one bench up)."""
+    N = nx * ny * nz
+    ptr = np.zeros(N + 1, dtype=np.int32)
+    idx = []
+    for b in range(N):
+        x, y, z = b % nx, (b // nx) % ny, b // (nx * ny)
+        lst = []
+        if z > 0:
+            for dx, dy in ((0, 0), (-1, 0), (1, 0), (0, -1), (0, 1)):
+                xa, ya = x + dx, y + dy
+                if 0 <= xa < nx and 0 <= ya < ny:
+                    lst.append(xa + nx * (ya + ny * (z - 1)))
+        lst.sort()
+        idx.extend(lst)
+        ptr[b + 1] = len(idx)
+    return ptr, np.asarray(idx, dtype=np.int32)
+
+
+def feasible_schedule_lists(N, T, pred_ptr, pred_idx, seed):
+    """Seeded schedule feasible under explicit predecessor lists whose
+    predecessors all have smaller indices: u_b uniform on 0..T, then in index
+    order p_b = max(u_b, p of every predecessor)."""
+    rng = np.random.default_rng(seed)
+    u = rng.integers(0, T + 1, size=N)
+    p = np.zeros(N, dtype=np.int64)
+    for b in range(N):
+        lo = 0
+        for k in range(pred_ptr[b], pred_ptr[b + 1]):
+            a = pred_idx[k]
+            assert a < b
+            lo = max(lo, p[a])
+        p[b] = max(u[b], lo)
+    return p.astype(np.int8)
+
+
+def with_precedence(inst, pred_ptr, pred_idx, p0=None):
+    """The instance with explicit predecessor lists (and optionally another
+    starting schedule)."""
+    import copy
+    out = copy.copy(inst)
+    out.pred_ptr = np.asarray(pred_ptr, dtype=np.int32)
+    out.pred_idx = np.asarray(pred_idx, dtype=np.int32)
+    if p0 is not None:
+        out.p0 = np.asarray(p0, dtype=np.int8)
+    return out
+

@@ -5,7 +5,10 @@ benchmark's CPU-baseline leg.  The product package never imports it.
 
 Instances are duck-typed: any object with nx, ny, nz, S, T, rate, lam,
 pen_proc, pen_mine, pcap, mcap, v (float32 [S][N]), ore (uint8 [S][N]) and
-ton (float64 [N]) attributes (the seeded generator's Instance has them).
+ton (float64 [N]) attributes (the seeded generator's Instance has them).  An
+instance may also carry explicit predecessor lists (Eq. 15's sets) as
+pred_ptr (int32 [N+1]) and pred_idx (int32 [pred_ptr[N]]); without them the
+precedence is the grid's 1-5 slope stencil.
 """
 from __future__ import annotations
 
@@ -39,7 +42,11 @@ class _Inst(C.Structure):
                 ("rate", C.c_double), ("lam", C.c_double),
                 ("pen_proc", C.c_double), ("pen_mine", C.c_double),
                 ("pcap", C.c_double), ("mcap", C.c_double),
-                ("v", C.c_void_p), ("ore", C.c_void_p), ("ton", C.c_void_p)]
+                ("v", C.c_void_p), ("ore", C.c_void_p), ("ton", C.c_void_p),
+                ("pred_ptr", C.c_void_p), ("pred_idx", C.c_void_p),
+                ("succ_ptr", C.c_void_p), ("succ_idx", C.c_void_p)]
+
+MAX_DEG = 9   # OR_MAX_DEG: predecessors (and successors) per block
 
 
 class _Obj(C.Structure):
@@ -64,6 +71,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         L.or_discount.argtypes = [i32, dbl, vp]
+        L.or_successor_csr.argtypes = [i64, vp, vp, vp, vp]
         L.or_predecessors.argtypes = [vp, i32, vp]
         L.or_predecessors.restype = i32
         L.or_successors.argtypes = [vp, i32, vp]
@@ -107,10 +115,29 @@ class Oracle:
         self.ton = np.ascontiguousarray(inst.ton, dtype=np.float64)
         assert self.v.shape == (self.S, self.N) and self.ore.shape == (self.S, self.N)
         assert self.ton.shape == (self.N,)
+        pp = getattr(inst, "pred_ptr", None)
+        ptrs = [None] * 4
+        if pp is not None:
+            self.pred_ptr = np.ascontiguousarray(pp, dtype=np.int32)
+            self.pred_idx = np.ascontiguousarray(inst.pred_idx, dtype=np.int32)
+            N = self.N
+            assert self.pred_ptr.shape == (N + 1,) and self.pred_ptr[0] == 0
+            assert np.all(np.diff(self.pred_ptr) >= 0)
+            assert np.all(np.diff(self.pred_ptr) <= MAX_DEG)
+            assert self.pred_idx.shape == (int(self.pred_ptr[-1]),)
+            assert np.all((self.pred_idx >= 0) & (self.pred_idx < N))
+            self.succ_ptr = np.empty(N + 1, dtype=np.int32)
+            self.succ_idx = np.empty(len(self.pred_idx), dtype=np.int32)
+            lib().or_successor_csr(N, _ptr(self.pred_ptr), _ptr(self.pred_idx),
+                                   _ptr(self.succ_ptr), _ptr(self.succ_idx))
+            assert np.all(np.diff(self.succ_ptr) <= MAX_DEG)
+            ptrs = [self.pred_ptr.ctypes.data, self.pred_idx.ctypes.data,
+                    self.succ_ptr.ctypes.data, self.succ_idx.ctypes.data]
         self.c = _Inst(int(inst.nx), int(inst.ny), int(inst.nz), self.S, self.T,
                        float(inst.rate), float(inst.lam), float(inst.pen_proc),
                        float(inst.pen_mine), float(inst.pcap), float(inst.mcap),
-                       self.v.ctypes.data, self.ore.ctypes.data, self.ton.ctypes.data)
+                       self.v.ctypes.data, self.ore.ctypes.data, self.ton.ctypes.data,
+                       *ptrs)
         self.ref = C.byref(self.c)
 
     def _p(self, p):
@@ -124,12 +151,12 @@ class Oracle:
         return d
 
     def predecessors(self, b):
-        out = np.empty(5, dtype=np.int32)
+        out = np.empty(MAX_DEG, dtype=np.int32)
         n = lib().or_predecessors(self.ref, int(b), _ptr(out))
         return sorted(out[:n].tolist())
 
     def successors(self, b):
-        out = np.empty(5, dtype=np.int32)
+        out = np.empty(MAX_DEG, dtype=np.int32)
         n = lib().or_successors(self.ref, int(b), _ptr(out))
         return sorted(out[:n].tolist())
 

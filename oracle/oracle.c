@@ -38,10 +38,16 @@ void or_discount(int32_t T, double rate, double *d) {
     d[T] = 0.0;
 }
 
-/* Direct predecessors (the set beta_b^Pred of Eq. 15) under the 1-5 slope
- * stencil: the block right above b and the four blocks sharing a face with
- * that block, all on the bench above, clipped at the grid edges. */
+/* Direct predecessors (the set beta_b^Pred of Eq. 15): the given lists when
+ * the instance carries them, else the 1-5 slope stencil: the block right
+ * above b and the four blocks sharing a face with that block, all on the
+ * bench above, clipped at the grid edges. */
 int32_t or_predecessors(const or_inst *I, int32_t b, int32_t *out) {
+    if (I->pred_ptr) {
+        int32_t n = 0;
+        for (int32_t k = I->pred_ptr[b]; k < I->pred_ptr[b + 1]; ++k) out[n++] = I->pred_idx[k];
+        return n;
+    }
     int32_t nx = I->nx, ny = I->ny;
     int32_t x = b % nx, y = (b / nx) % ny, z = b / (nx * ny);
     if (z == 0) return 0;
@@ -56,8 +62,14 @@ int32_t or_predecessors(const or_inst *I, int32_t b, int32_t *out) {
     return n;
 }
 
-/* Successors: every block c with b among the predecessors of c. */
+/* Successors: every block c with b among the predecessors of c (the
+ * transposed lists when the instance carries them). */
 int32_t or_successors(const or_inst *I, int32_t b, int32_t *out) {
+    if (I->pred_ptr) {
+        int32_t n = 0;
+        for (int32_t k = I->succ_ptr[b]; k < I->succ_ptr[b + 1]; ++k) out[n++] = I->succ_idx[k];
+        return n;
+    }
     int32_t nx = I->nx, ny = I->ny, nz = I->nz;
     int32_t x = b % nx, y = (b / nx) % ny, z = b / (nx * ny);
     int32_t n = 0;
@@ -66,12 +78,26 @@ int32_t or_successors(const or_inst *I, int32_t b, int32_t *out) {
         for (int32_t xc = x - 1; xc <= x + 1; ++xc) {
             if (xc < 0 || xc >= nx || yc < 0 || yc >= ny) continue;
             int32_t c = xc + nx * (yc + ny * (z + 1));
-            int32_t pr[5];
+            int32_t pr[OR_MAX_DEG];
             int32_t np = or_predecessors(I, c, pr);
             for (int32_t k = 0; k < np; ++k)
                 if (pr[k] == b) out[n++] = c;
         }
     return n;
+}
+
+void or_successor_csr(int64_t N, const int32_t *pred_ptr, const int32_t *pred_idx,
+                      int32_t *succ_ptr, int32_t *succ_idx) {
+    for (int64_t b = 0; b <= N; ++b) succ_ptr[b] = 0;
+    for (int64_t c = 0; c < N; ++c)
+        for (int32_t k = pred_ptr[c]; k < pred_ptr[c + 1]; ++k) ++succ_ptr[pred_idx[k] + 1];
+    for (int64_t b = 0; b < N; ++b) succ_ptr[b + 1] += succ_ptr[b];
+    int32_t *fill = malloc(sizeof(int32_t) * (N > 0 ? N : 1));
+    for (int64_t b = 0; b < N; ++b) fill[b] = succ_ptr[b];
+    for (int64_t c = 0; c < N; ++c)   /* increasing c: each list comes out sorted */
+        for (int32_t k = pred_ptr[c]; k < pred_ptr[c + 1]; ++k)
+            succ_idx[fill[pred_idx[k]]++] = (int32_t)c;
+    free(fill);
 }
 
 static void mean_std(const double *x, int32_t n, double *mu, double *sd) {
@@ -125,7 +151,7 @@ void or_objective(const or_inst *I, const int8_t *p, or_objective_t *out,
     pm = I->pen_mine * pm;
     int64_t nv = 0;
     for (int64_t b = 0; b < N; ++b) {
-        int32_t pr[5];
+        int32_t pr[OR_MAX_DEG];
         int32_t np = or_predecessors(I, (int32_t)b, pr);
         for (int32_t k = 0; k < np; ++k)
             if (p[pr[k]] > p[b]) ++nv;
@@ -168,7 +194,7 @@ static void eval_one(const or_inst *I, const int8_t *p, const double *Ns,
     if (t == pb) f |= OR_NOOP;
 
     int prec_ok = 1;
-    int32_t nb[5];
+    int32_t nb[OR_MAX_DEG];
     int32_t n = or_predecessors(I, b, nb);
     for (int32_t k = 0; k < n; ++k)
         if (p[nb[k]] > t) prec_ok = 0;
@@ -417,7 +443,7 @@ double or_relaxed_d(const or_inst *I, const double *x, const or_relax_t *rp,
     }
     pm = rp->mu_mine * pm;
     for (int64_t b = 0; b < N; ++b) {
-        int32_t pa[5];
+        int32_t pa[OR_MAX_DEG];
         int32_t np = or_predecessors(I, (int32_t)b, pa);
         for (int32_t k = 0; k < np; ++k)
             for (int32_t t = 0; t < T; ++t) {
@@ -450,7 +476,7 @@ double or_relaxed_d(const or_inst *I, const double *x, const or_relax_t *rp,
                 grad[b * T + t] = gy[t] - (t + 1 < T ? gy[t + 1] : 0.0);
         }
         for (int64_t b = 0; b < N; ++b) {
-            int32_t nb[5];
+            int32_t nb[OR_MAX_DEG];
             int32_t np = or_predecessors(I, (int32_t)b, nb);
             for (int32_t t = 0; t < T; ++t) {
                 double acc = 0.0;
@@ -493,7 +519,7 @@ int32_t or_rank_moves(const or_inst *I, const int8_t *p, const double *grad,
     sidx_t *a = malloc(sizeof(sidx_t) * N * D);
     double *Gc = malloc(sizeof(double) * D);
     int64_t m = 0;
-    int32_t nb[5];
+    int32_t nb[OR_MAX_DEG];
     for (int64_t b = 0; b < N; ++b) {
         Gc[0] = 0.0;
         for (int32_t t = 0; t < T; ++t) Gc[t + 1] = Gc[t] + grad[b * T + t];
@@ -637,10 +663,10 @@ static void opt_rec(opt_ctx *c, int32_t b) {
         }
         return;
     }
-    int32_t pr[5];
+    int32_t pr[OR_MAX_DEG];
     int32_t np = or_predecessors(I, b, pr);
     int32_t lo = 0;
-    for (int32_t k = 0; k < np; ++k)   /* predecessors have smaller indices */
+    for (int32_t k = 0; k < np; ++k)   /* predecessors have smaller indices (checked) */
         if (c->p[pr[k]] > lo) lo = c->p[pr[k]];
     for (int32_t t = lo; t <= I->T; ++t) {
         c->p[b] = (int8_t)t;
@@ -650,6 +676,12 @@ static void opt_rec(opt_ctx *c, int32_t b) {
 
 double or_optimum(const or_inst *I, int8_t *p_best, int64_t *n_feasible) {
     int64_t N = n_blocks(I);
+    for (int64_t b = 0; b < N; ++b) {
+        int32_t pr[OR_MAX_DEG];
+        int32_t np = or_predecessors(I, (int32_t)b, pr);
+        for (int32_t k = 0; k < np; ++k)
+            if (pr[k] >= b) return NAN;
+    }
     opt_ctx c;
     c.I = I;
     c.p = calloc((size_t)N, 1);

@@ -32,7 +32,15 @@ typedef struct {
     const float *v;       /* [S][N] block values */
     const uint8_t *ore;   /* [S][N] 0/1: processed in that scenario */
     const double *ton;    /* [N] tonnage */
+    /* General precedence (the sets beta_b^Pred of Eq. 15 given explicitly):
+     * the predecessors of b are pred_idx[pred_ptr[b] .. pred_ptr[b+1]), its
+     * successors succ_idx[succ_ptr[b] .. succ_ptr[b+1]) (the transpose, from
+     * or_successor_csr).  All four NULL: the 1-5 slope stencil of the grid.
+     * At most OR_MAX_DEG of each per block. */
+    const int32_t *pred_ptr, *pred_idx, *succ_ptr, *succ_idx;
 } or_inst;
+
+#define OR_MAX_DEG 9
 
 typedef struct {
     double mu, sigma, R, Pp, Pm, J;
@@ -44,8 +52,14 @@ typedef struct {
 } or_relax_t;
 
 void or_discount(int32_t T, double rate, double *d /* [T+1] */);
-int32_t or_predecessors(const or_inst *I, int32_t b, int32_t *out /* [5] */);
-int32_t or_successors(const or_inst *I, int32_t b, int32_t *out /* [5] */);
+int32_t or_predecessors(const or_inst *I, int32_t b, int32_t *out /* [OR_MAX_DEG] */);
+int32_t or_successors(const or_inst *I, int32_t b, int32_t *out /* [OR_MAX_DEG] */);
+
+/* Successor lists of a predecessor CSR: c is a successor of b iff b is a
+ * predecessor of c; each list in increasing c.  succ_ptr [N+1], succ_idx
+ * [pred_ptr[N]]. */
+void or_successor_csr(int64_t N, const int32_t *pred_ptr, const int32_t *pred_idx,
+                      int32_t *succ_ptr, int32_t *succ_idx);
 
 /* Full objective of schedule p.  Ns [S], O [S][T], M [T] may be NULL. */
 void or_objective(const or_inst *I, const int8_t *p, or_objective_t *out,
@@ -97,7 +111,9 @@ double or_search(const or_inst *I, int8_t *p, int32_t mode, int32_t k,
 
 /* Exhaustive optimum over every precedence-feasible schedule (tiny grids).
  * Returns J*; p_best gets the lexicographically smallest maximiser;
- * *n_feasible the number of feasible schedules. */
+ * *n_feasible the number of feasible schedules.  Every predecessor must have
+ * a smaller index than its successor (true of the grid stencil); otherwise
+ * NaN is returned. */
 double or_optimum(const or_inst *I, int8_t *p_best, int64_t *n_feasible);
 
 #endif
