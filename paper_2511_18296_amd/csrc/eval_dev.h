@@ -240,8 +240,13 @@ __device__ __forceinline__ TablePrefetch issue_tables(const DevModel &m) {
     f.fa = tid < TW ? gld(m.tab.full_add + tid) : 0u;
     f.fr = tid < TW ? gld(m.tab.full_rem + tid) : 0u;
     f.rg = tid < 4 * T ? gld(m.tab.rng + tid) : 0;
-    if (kLists) f.ae = gld(m.tab.add_packed + min(tid, kListCap - 1));
-    f.re = gld(m.tab.rem_packed + min(tid, kListCap - 1));
+    // the packed lists hold T*S entries each: lanes past that load nothing
+    // (their LDS slots are never read, the list ranges end before them)
+    const bool in_list = tid < kListCap && tid < T * m.S;
+    f.ae = AddEntry{0.0, 0.0f, 0};
+    f.re = RemEntry{0.0f, 0};
+    if (kLists && in_list) f.ae = gld(m.tab.add_packed + tid);
+    if (in_list) f.re = gld(m.tab.rem_packed + tid);
     return f;
 }
 
