@@ -99,6 +99,13 @@ def test_autograd_function_matches_adjoint():
 
 
 def test_rank_moves_against_oracle_ranking():
+    """Top-4,096 gradient-ranked moves at x(p) of the 54,000-block instance
+    against the oracle's ranking of the same gradient.  Both sides sum the
+    FP32 gradient in FP64; the GPU then rounds each gain to FP32 and ranks the
+    rounded values, so the two orders may differ only between moves whose FP64
+    gains lie within one FP32 rounding of each other.  Every index in either
+    list but not both, and every position where the lists differ, must be such
+    a tie."""
     inst = instance("largest")
     m = gpu_model(inst)
     x = torch.from_numpy(mpsgen.integer_x(inst.p0, inst.T)).cuda()
@@ -109,26 +116,38 @@ def test_rank_moves_against_oracle_ranking():
     blk, per, gain, cnt = m.rank_moves(g, k)
     assert int(cnt.item()) == k
     o = oracle.Oracle(inst)
-    ob, ot, og = o.rank_moves(inst.p0, to_np(g).astype(np.float64), k)
     D = inst.T + 1
+    g64 = to_np(g).astype(np.float64)
+    # the oracle's gain of EVERY feasible non-no-op move, in its ranked order
+    ab, at, ag = o.rank_moves(inst.p0, g64, inst.N * D)
+    full = np.full(inst.N * D, -np.inf)
+    full[ab.astype(np.int64) * D + at] = ag
+    oi = ab[:k].astype(np.int64) * D + at[:k]
+    og = ag[:k]
     gi = to_np(blk).astype(np.int64) * D + to_np(per)
-    oi = ob.astype(np.int64) * D + ot
-    np.testing.assert_allclose(to_np(gain), og, rtol=1e-6, atol=1e-6 * np.abs(og).max())
-    if not np.array_equal(gi, oi):
-        kth = og[-1]
-        for i in set(gi) ^ set(oi):
-            assert abs(float(og[np.searchsorted(-og, -kth)]) - kth) <= 1e-6 * abs(kth) + 1e-3
-    assert len(set(gi) & set(oi)) >= k - 8
+    gg = to_np(gain).astype(np.float64)
+    # every GPU move is feasible and its gain is the FP64 gain rounded to FP32
+    assert np.all(np.isfinite(full[gi])), "GPU ranked a move the oracle excludes"
+    ulp = np.spacing(np.abs(full[gi]).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(gg - full[gi]) <= 0.5 * ulp + 1e-9 * np.abs(full[gi]))
+    assert np.all(np.diff(gg) <= 0), "GPU gains are not in descending order"
+    # tie bound: one FP32 rounding at the k-th gain's magnitude (both ends)
+    kth = og[-1]
+    eps = 2.0 * float(np.spacing(np.float32(max(abs(kth), abs(og[0])))))
+    for i in set(gi.tolist()) ^ set(oi.tolist()):
+        assert abs(full[i] - kth) <= eps, (i, full[i], kth, eps)
+    diff = np.nonzero(gi != oi)[0]
+    for j in diff:
+        assert abs(full[gi[j]] - full[oi[j]]) <= eps, (j, full[gi[j]], full[oi[j]], eps)
+    print(f"rank: {len(diff)} positions differ, {len(set(gi.tolist()) ^ set(oi.tolist()))} "
+          f"indices in one list only, tie bound {eps:.3g} at k-th gain {kth:.6g}")
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("name", ["tight", "one_period", "max_periods"])
-def test_search_reaches_oracle_quality(name, mode):
-    inst = instance(name)
+def _search_case(inst, mode, k):
     m = gpu_model(inst)
-    st = m.search(mode, 256, RELAX)
+    st = m.search(mode, k, RELAX)
     o = oracle.Oracle(inst)
-    q_o, J_o, st_o = o.search(inst.p0, mode, 256, RELAX)
+    q_o, J_o, st_o = o.search(inst.p0, mode, k, RELAX)
     p = to_np(m.get_schedule())
     obj = o.objective(p)
     assert obj["n_prec_viol"] == 0
@@ -140,6 +159,28 @@ def test_search_reaches_oracle_quality(name, mode):
     # J can sit near zero when the penalties offset the NPV: measure the gap
     # on the scale of the larger of |J| and |mu|
     rel = abs(st["J"] - J_o) / max(abs(J_o), abs(obj["mu"]))
-    print(f"{name} mode {mode}: GPU J {st['J']:.8g} vs oracle {J_o:.8g} (rel {rel:.2g}), "
-          f"{st['iterations']} rounds, {st['evaluations']} evaluations")
-    assert rel <= 1e-3
+    print(f"mode {mode}: GPU J {st['J']:.12g} vs oracle {J_o:.12g} (rel {rel:.2g}), "
+          f"{st['iterations']} rounds ({st_o['iterations']} in the oracle), "
+          f"{st['evaluations']} evaluations ({st_o['evaluations']}), "
+          f"{int(np.count_nonzero(p != q_o))} blocks differ")
+    return p, q_o, rel, st, st_o
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("name", ["tight", "one_period", "max_periods"])
+def test_search_reaches_oracle_quality(name, mode):
+    """Both search loops on the GPU end at the oracle's schedule, block for
+    block, with the same number of rounds."""
+    p, q_o, rel, st, st_o = _search_case(instance(name), mode, 256)
+    np.testing.assert_array_equal(p, q_o)
+    assert rel <= 1e-12
+    assert st["iterations"] == st_o["iterations"]
+
+
+def test_exhaustive_search_at_full_size():
+    """The exhaustive loop (evaluate all 1,134,000 moves, top 4,096, repair,
+    until nothing applies) on the 54,000-block instance against the oracle's
+    run of the same loop."""
+    p, q_o, rel, st, st_o = _search_case(instance("largest"), 0, 4096)
+    np.testing.assert_array_equal(p, q_o)
+    assert rel <= 1e-12
