@@ -193,6 +193,20 @@ mps_status mps_topk(const float *score, const uint8_t *flags, int64_t n,
                     float *top_score, int32_t *count, void *ws,
                     size_t ws_bytes, void *stream);
 
+/* mps_topk for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same selection and outputs, with the workspace in a device array the
+ * library owns (about 33 MiB per device, held until the process ends)
+ * instead of a caller buffer.  Limits: 0 <= n <= 2^21 (2,097,152 items),
+ * 1 <= k <= MPS_MAX_TOPK; beyond them MPS_E_INVALID_ARG before any work.
+ * Runs on the current device; allocates nothing.  Every call on one device
+ * shares that device's array: calls that overlap in time on one device
+ * (another stream, another thread) race and must be serialised by the
+ * caller. */
+mps_status mps_topk_noalloc(const float *score, const uint8_t *flags, int64_t n,
+                            int32_t k, uint8_t require, uint8_t forbid, int64_t *idx,
+                            float *top_score, int32_t *count, void *stream);
+
 /* Greedy repair (Alg. 4 amortised over an ordered candidate list): walk the
  * candidates idx[0 .. *count) (device int32 count, at most max_cand) that
  * index into `moves`, in order; skip a block already moved in this call;

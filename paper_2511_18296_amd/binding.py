@@ -93,6 +93,7 @@ def _load():
         "mps_topk_ws_bytes": ([i64, i32], C.c_size_t),
         "mps_topk": ([vp, vp, i64, i32, C.c_uint8, C.c_uint8, vp, vp, vp, vp,
                       C.c_size_t, vp], st),
+        "mps_topk_noalloc": ([vp, vp, i64, i32, C.c_uint8, C.c_uint8, vp, vp, vp, vp], st),
         "mps_repair": ([vp, vp, vp, vp, i32, i32, vp, vp], st),
         "mps_relaxed_saved_bytes": ([vp], C.c_size_t),
         "mps_relaxed_fwd": ([vp, vp, vp, vp, vp, vp], st),
@@ -125,7 +126,7 @@ lib = _load()
 EXPORTS = ("mps_last_error", "mps_version", "mps_device_count", "mps_build_model",
            "mps_destroy_model", "mps_model_dims", "mps_set_schedule",
            "mps_get_schedule", "mps_get_objective", "mps_objective_async",
-           "mps_eval_moves", "mps_topk_ws_bytes", "mps_topk", "mps_repair",
+           "mps_eval_moves", "mps_topk_ws_bytes", "mps_topk", "mps_topk_noalloc", "mps_repair",
            "mps_relaxed_saved_bytes", "mps_relaxed_fwd", "mps_relaxed_bwd",
            "mps_rank_ws_bytes", "mps_rank_moves", "mps_search", "mps_state_bytes",
            "mps_state_save", "mps_state_restore", "mps_batch_create", "mps_batch_destroy",
@@ -386,6 +387,22 @@ class TopK:
                            _ptr(self.idx), _ptr(self.score), _ptr(self.count),
                            _ptr(self.ws), self.ws_bytes, _stream(stream)))
         return self.idx, self.score, self.count
+
+
+def topk_noalloc(score, flags, idx, top_score, count, require=PREC_OK, forbid=NOOP | BAD,
+                 stream=None):
+    """mps_topk with the library-owned workspace: writes the caller's idx
+    (int64 [k]), top_score (float32 [k] or None) and count (int32 [1])."""
+    _dev(score, torch.float32, None, "score")
+    _dev(flags, torch.uint8, score.shape, "flags")
+    _dev(idx, torch.int64, None, "idx")
+    _dev(count, torch.int32, (1,), "count")
+    if top_score is not None:
+        _dev(top_score, torch.float32, idx.shape, "top_score")
+    check(lib.mps_topk_noalloc(_ptr(score), _ptr(flags), int(score.shape[0]),
+                               int(idx.shape[0]), require, forbid, _ptr(idx),
+                               _ptr(top_score), _ptr(count), _stream(stream)))
+    return idx, top_score, count
 
 
 def topk(score, flags, k, require=PREC_OK, forbid=NOOP | BAD, stream=None):

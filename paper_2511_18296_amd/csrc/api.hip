@@ -86,6 +86,12 @@ struct SearchBufs {
 
 }  // namespace
 
+// Status reporting for entry points defined in other translation units.
+mps_status mps::report_error(mps_status st, const char *msg) {
+    g_err = msg;
+    return st;
+}
+
 struct mps_model {
     int device = 0;
     mps_params prm{};

@@ -85,6 +85,9 @@ struct DevModel {
     int32_t *blk_info;     // [N] p | maxPred << 8 | minSucc << 16
 };
 
+// Sets the thread-local text mps_last_error() returns; returns st.
+mps_status report_error(mps_status st, const char *msg);
+
 // Launch wrappers (each returns the hipError_t of its launches).
 hipError_t launch_block_stats(const DevModel &m, float *mb32, float *Vb32,
                               double *mb64, double *Vb64, hipStream_t st);

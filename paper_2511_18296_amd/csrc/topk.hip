@@ -23,6 +23,9 @@
 // depend on thread timing.
 #include <float.h>
 #include <math.h>
+#include <stdio.h>
+
+#include <mutex>
 
 #include "topk_dev.h"
 
@@ -394,3 +397,82 @@ hipError_t launch_topk(const float *score, const uint8_t *flags, int64_t n, int3
 }
 
 }  // namespace mps
+
+// ---- top-k with a library-owned workspace ------------------------------------
+// The selection above with its workspace in a device array of this library
+// instead of a caller buffer, for callers that cannot allocate.  The array is
+// sized for kNoAllocMaxN items and k <= MPS_MAX_TOPK; each device holds its
+// own copy for the life of the process.  k_topk_init clears what must start
+// at zero on every call, so no call depends on what the previous one left.
+
+namespace mps {
+
+constexpr int64_t kNoAllocMaxN = (int64_t)1 << 21;
+constexpr size_t ca256(size_t x) { return (x + 255) & ~(size_t)255; }
+// the layout carve_ws makes for (kNoAllocMaxN, MPS_MAX_TOPK)
+constexpr size_t kScratchBytes =
+    ca256(sizeof(TopkCtrl)) + ca256(sizeof(uint32_t) * kBins * kRep) +
+    ca256(sizeof(uint64_t) * MPS_MAX_TOPK) + 2 * ca256(sizeof(uint64_t) * kNoAllocMaxN) +
+    ca256(sizeof(uint32_t) * ((MPS_MAX_TOPK + kRankTile - 1) / kRankTile) * MPS_MAX_TOPK);
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of this device's copy of `scratch` (the host-side name is
+// only a stand-in and must never reach a kernel).  Looked up once per device.
+static hipError_t scratch_address(int dev, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace mps
+
+extern "C" mps_status mps_topk_noalloc(const float *score, const uint8_t *flags, int64_t n,
+                                       int32_t k, uint8_t require, uint8_t forbid,
+                                       int64_t *idx, float *top_score, int32_t *count,
+                                       void *stream) {
+    using namespace mps;
+    char msg[160];
+    if (k < 1 || k > MPS_MAX_TOPK) {
+        snprintf(msg, sizeof(msg), "k must be in 1..%d (got %d)", MPS_MAX_TOPK, k);
+        return report_error(MPS_E_INVALID_ARG, msg);
+    }
+    if (n < 0 || n > kNoAllocMaxN) {
+        snprintf(msg, sizeof(msg),
+                 "n = %lld exceeds the %lld items the library-owned top-k workspace holds",
+                 (long long)n, (long long)kNoAllocMaxN);
+        return report_error(MPS_E_INVALID_ARG, msg);
+    }
+    if ((n > 0 && (!score || !flags)) || !idx || !count)
+        return report_error(MPS_E_INVALID_ARG, "score, flags, idx and count are required");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        snprintf(msg, sizeof(msg), "no usable current device (%s)", hipGetErrorString(e));
+        return report_error(MPS_E_DEVICE, msg);
+    }
+    void *ws = nullptr;
+    e = scratch_address(dev, &ws);
+    if (e != hipSuccess) {
+        snprintf(msg, sizeof(msg), "address of the top-k scratch: %s", hipGetErrorString(e));
+        return report_error(MPS_E_DEVICE, msg);
+    }
+    e = launch_topk(score, flags, n, k, require, forbid, idx, top_score, count, ws,
+                    (hipStream_t)stream);
+    if (e != hipSuccess) {
+        snprintf(msg, sizeof(msg), "topk: %s", hipGetErrorString(e));
+        return report_error(MPS_E_DEVICE, msg);
+    }
+    return MPS_OK;
+}
