@@ -44,7 +44,8 @@ class _Inst(C.Structure):
                 ("pcap", C.c_double), ("mcap", C.c_double),
                 ("v", C.c_void_p), ("ore", C.c_void_p), ("ton", C.c_void_p),
                 ("pred_ptr", C.c_void_p), ("pred_idx", C.c_void_p),
-                ("succ_ptr", C.c_void_p), ("succ_idx", C.c_void_p)]
+                ("succ_ptr", C.c_void_p), ("succ_idx", C.c_void_p),
+                ("mult", C.c_void_p), ("risk", C.c_int32), ("alpha", C.c_double)]
 
 MAX_DEG = 9   # OR_MAX_DEG: predecessors (and successors) per block
 
@@ -93,6 +94,14 @@ def lib():
         L.or_rank_moves.restype = i32
         L.or_search.argtypes = [vp, vp, i32, i32, vp, i32, vp, i32]
         L.or_search.restype = dbl
+        L.or_repair_cascade.argtypes = [vp, vp, i32, vp, vp, i32, i32, vp, vp, vp]
+        L.or_repair_cascade.restype = i32
+        L.or_cvar.argtypes = [vp, i32, dbl]
+        L.or_cvar.restype = dbl
+        L.or_lns_sa.argtypes = [vp, vp, i32, i32, i32, i32, dbl, dbl, dbl, vp, vp, vp, i32]
+        L.or_lns_sa.restype = dbl
+        L.or_greedy_init.argtypes = [vp, vp, i32, vp]
+        L.or_greedy_init.restype = i32
         L.or_optimum.argtypes = [vp, vp, vp]
         L.or_optimum.restype = dbl
         _lib = L
@@ -133,11 +142,20 @@ class Oracle:
             assert np.all(np.diff(self.succ_ptr) <= MAX_DEG)
             ptrs = [self.pred_ptr.ctypes.data, self.pred_idx.ctypes.data,
                     self.succ_ptr.ctypes.data, self.succ_idx.ctypes.data]
+        mult = getattr(inst, "mult", None)
+        self.mult = None
+        if mult is not None:
+            self.mult = np.ascontiguousarray(mult, dtype=np.float64)
+            assert self.mult.shape == (self.S, self.T)
+        risk = int(getattr(inst, "risk", 0))
+        alpha = float(getattr(inst, "alpha", 0.1))
+        assert risk in (0, 1) and 0.0 < alpha <= 1.0
         self.c = _Inst(int(inst.nx), int(inst.ny), int(inst.nz), self.S, self.T,
                        float(inst.rate), float(inst.lam), float(inst.pen_proc),
                        float(inst.pen_mine), float(inst.pcap), float(inst.mcap),
                        self.v.ctypes.data, self.ore.ctypes.data, self.ton.ctypes.data,
-                       *ptrs)
+                       *ptrs, self.mult.ctypes.data if self.mult is not None else None,
+                       risk, alpha)
         self.ref = C.byref(self.c)
 
     def _p(self, p):
@@ -209,6 +227,18 @@ class Oracle:
                             int(bool(hard)), C.byref(J), _ptr(acc))
         return q, int(a), J.value, acc
 
+    def repair_cascade(self, p, cand_block, cand_period, hard=False, max_set=64):
+        q = self._p(p).copy()
+        cb = np.ascontiguousarray(cand_block, dtype=np.int32)
+        ct = np.ascontiguousarray(cand_period, dtype=np.int8)
+        acc = np.zeros(cb.shape[0], dtype=np.uint8)
+        size = np.zeros(cb.shape[0], dtype=np.int32)
+        J = C.c_double()
+        a = lib().or_repair_cascade(self.ref, _ptr(q), cb.shape[0], _ptr(cb), _ptr(ct),
+                                    int(bool(hard)), int(max_set), C.byref(J), _ptr(acc),
+                                    _ptr(size))
+        return q, int(a), J.value, acc, size
+
     def relaxed(self, x, mu_proc, mu_mine, mu_prec, grad=True):
         x = np.ascontiguousarray(x)
         assert x.shape == (self.N, self.T)
@@ -242,11 +272,38 @@ class Oracle:
         return q, J, dict(iterations=int(stats[0]), evaluations=int(stats[1]),
                           applied=int(stats[2]))
 
+    def greedy_init(self, max_pass=1000):
+        p = np.empty(self.N, dtype=np.int8)
+        placed = C.c_int64()
+        passes = lib().or_greedy_init(self.ref, _ptr(p), int(max_pass), C.byref(placed))
+        return p, int(passes), int(placed.value)
+
+    def lns_sa(self, p, n_iter, nb, k, max_rounds, eps_max, temp0, cool, u, threads=0):
+        """LNS + SA driver; returns (best schedule, J_best, trajectory, stats)."""
+        q = self._p(p).copy()
+        kx = (int(self.inst.nx) + nb - 1) // nb
+        ky = (int(self.inst.ny) + nb - 1) // nb
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        assert u.shape == (n_iter * kx * ky,)
+        traj = np.zeros((n_iter * kx * ky, 4))
+        stats = np.zeros(4, dtype=np.int64)
+        J = lib().or_lns_sa(self.ref, _ptr(q), int(n_iter), int(nb), int(k), int(max_rounds),
+                            float(eps_max), float(temp0), float(cool), _ptr(u), _ptr(traj),
+                            _ptr(stats), int(threads))
+        return q, J, traj, dict(steps=int(stats[0]), accepted=int(stats[1]),
+                                evaluations=int(stats[2]), applied=int(stats[3]))
+
     def optimum(self):
         best = np.zeros(self.N, dtype=np.int8)
         cnt = C.c_int64()
         J = lib().or_optimum(self.ref, _ptr(best), C.byref(cnt))
         return J, best, int(cnt.value)
+
+
+def cvar(x, alpha):
+    """CVaR of the lower alpha tail of x (or_cvar)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return lib().or_cvar(_ptr(x), x.shape[0], float(alpha))
 
 
 def topk(score, flags, k, req=PREC_OK, forbid=NOOP | BAD):

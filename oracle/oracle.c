@@ -100,6 +100,34 @@ void or_successor_csr(int64_t N, const int32_t *pred_ptr, const int32_t *pred_id
     free(fill);
 }
 
+/* Discounted multiplier of scenario s in period t: d(t) sigma(s,t), and 0
+ * for "never" (Eq. 12 with the paper's discounting; sigma = 1 without a
+ * multiplier table). */
+static double wdisc(const or_inst *I, const double *d, int32_t s, int32_t t) {
+    if (t >= I->T) return 0.0;
+    return I->mult ? d[t] * I->mult[(int64_t)s * I->T + t] : d[t];
+}
+
+static int cmp_dbl(const void *pa, const void *pb) {
+    double a = *(const double *)pa, b = *(const double *)pb;
+    return (a > b) - (a < b);
+}
+
+double or_cvar(const double *x, int32_t n, double alpha) {
+    double *y = malloc(sizeof(double) * n);
+    memcpy(y, x, sizeof(double) * n);
+    qsort(y, (size_t)n, sizeof(double), cmp_dbl);
+    double an = alpha * n;
+    int32_t k = (int32_t)ceil(an);
+    if (k < 1) k = 1;
+    if (k > n) k = n;
+    double acc = 0.0;
+    for (int32_t i = 0; i < k - 1; ++i) acc += y[i];
+    acc += (an - (k - 1)) * y[k - 1];
+    free(y);
+    return acc / an;
+}
+
 static void mean_std(const double *x, int32_t n, double *mu, double *sd) {
     double s = 0.0;
     for (int32_t i = 0; i < n; ++i) s += x[i];
@@ -111,6 +139,13 @@ static void mean_std(const double *x, int32_t n, double *mu, double *sd) {
 }
 
 static double hinge(double x, double cap) { return x > cap ? x - cap : 0.0; }
+
+/* Risk-adjusted value of the scenario NPVs: mu - lambda*sigma, or with the
+ * CVaR measure mu - lambda*(mu - CVaR_alpha). */
+static double risk_value(const or_inst *I, const double *Ns, double mu, double sd) {
+    if (I->risk == 1) return mu - I->lambda * (mu - or_cvar(Ns, I->S, I->alpha));
+    return mu - I->lambda * sd;
+}
 
 /* Per-scenario NPV, period tonnages and the objective (Eq. 14 expectation,
  * extended by the risk term and the capacity penalties):
@@ -131,7 +166,7 @@ void or_objective(const or_inst *I, const int8_t *p, or_objective_t *out,
     or_discount(T, I->rate, d);
     for (int32_t s = 0; s < S; ++s) {
         double acc = 0.0;
-        for (int64_t b = 0; b < N; ++b) acc += val(I, s, (int32_t)b) * d[p[b]];
+        for (int64_t b = 0; b < N; ++b) acc += val(I, s, (int32_t)b) * wdisc(I, d, s, p[b]);
         Ns[s] = acc;
     }
     for (int64_t b = 0; b < N; ++b) {
@@ -158,7 +193,7 @@ void or_objective(const or_inst *I, const int8_t *p, or_objective_t *out,
     }
     out->mu = mu;
     out->sigma = sd;
-    out->R = mu - I->lambda * sd;
+    out->R = risk_value(I, Ns, mu, sd);
     out->Pp = pp;
     out->Pm = pm;
     out->J = out->R - pp - pm;
@@ -212,11 +247,11 @@ static void eval_one(const or_inst *I, const int8_t *p, const double *Ns,
     if (proc_ok) f |= OR_PROC_OK;
 
     /* Risk-adjusted expected NPV of p' from scratch. */
-    double dd = d[t] - d[pb];
-    for (int32_t s = 0; s < S; ++s) Np[s] = Ns[s] + val(I, s, b) * dd;
+    for (int32_t s = 0; s < S; ++s)
+        Np[s] = Ns[s] + val(I, s, b) * (wdisc(I, d, s, t) - wdisc(I, d, s, pb));
     double mu2, sd2;
     mean_std(Np, S, &mu2, &sd2);
-    double dR = (mu2 - I->lambda * sd2) - (mu - I->lambda * sd);
+    double dR = risk_value(I, Np, mu2, sd2) - risk_value(I, Ns, mu, sd);
 
     double dPp = 0.0, dPm = 0.0;
     if (t != pb) {
@@ -364,8 +399,8 @@ int32_t or_repair(const or_inst *I, int8_t *p, int32_t n_cand,
         if (hard_capacity) ok = ok && (f & OR_MINE_OK) && (f & OR_PROC_OK);
         if (!ok || !(score > 0.0)) continue;
         int32_t pb = p[b];
-        double dd = d[t] - d[pb];
-        for (int32_t s = 0; s < S; ++s) Ns[s] += val(I, s, b) * dd;
+        for (int32_t s = 0; s < S; ++s)
+            Ns[s] += val(I, s, b) * (wdisc(I, d, s, t) - wdisc(I, d, s, pb));
         for (int32_t s = 0; s < S; ++s) {
             if (!ore(I, s, b)) continue;
             if (pb < T) O[(int64_t)s * T + pb] -= I->ton[b];
@@ -693,4 +728,355 @@ double or_optimum(const or_inst *I, int8_t *p_best, int64_t *n_feasible) {
     free(c.p);
     if (n_feasible) *n_feasible = c.count;
     return c.J_best;
+}
+
+/* ---- greedy initializer (Alg. 3 with every uncertainty factor equal to 1) --
+ * Blocks are ranked by value density, here the block's expected value
+ * vd[b] = mean_s v[s,b] (grade times mass priced by the value model), in
+ * descending order with ties to the smaller index.  Starting from "nothing
+ * mined", each block in that order takes the earliest period t < T in which
+ * it is feasible against the schedule built so far: every predecessor mined
+ * in t or earlier (an unplaced predecessor counts as never mined), every
+ * placed successor in t or later, the mining tonnage of t plus the block
+ * within Mcap, and in every scenario in which the block is ore the processed
+ * tonnage of t plus the block within Pcap -- the PREC_OK, MINE_OK and PROC_OK
+ * conditions of a move (b, t).  A block with no such period stays unplaced.
+ * The printed loop is one pass; a block whose predecessors rank below it can
+ * only be placed in a later pass, so passes repeat over the unplaced blocks,
+ * in the same order, until one places nothing (or max_pass passes ran). */
+typedef struct { double vd; int32_t b; } vdb_t;
+
+static int cmp_vdb(const void *pa, const void *pb) {
+    const vdb_t *a = pa, *b = pb;
+    if (a->vd > b->vd) return -1;
+    if (a->vd < b->vd) return 1;
+    return (a->b > b->b) - (a->b < b->b);
+}
+
+int32_t or_greedy_init(const or_inst *I, int8_t *p, int32_t max_pass, int64_t *n_placed) {
+    int64_t N = n_blocks(I);
+    int32_t S = I->S, T = I->T;
+    vdb_t *ord = malloc(sizeof(vdb_t) * (N > 0 ? N : 1));
+    double *O = calloc((size_t)S * T, sizeof(double));
+    double *M = calloc((size_t)T, sizeof(double));
+    for (int64_t b = 0; b < N; ++b) {
+        double acc = 0.0;
+        for (int32_t s = 0; s < S; ++s) acc += val(I, s, (int32_t)b);
+        ord[b].vd = acc / S;
+        ord[b].b = (int32_t)b;
+        p[b] = (int8_t)T;
+    }
+    qsort(ord, (size_t)N, sizeof(vdb_t), cmp_vdb);
+    int32_t passes = 0;
+    int64_t placed = 0;
+    while (passes < max_pass) {
+        ++passes;
+        int64_t now = 0;
+        for (int64_t i = 0; i < N; ++i) {
+            int32_t b = ord[i].b;
+            if (p[b] != T) continue;
+            double ton = I->ton[b];
+            int32_t nb[OR_MAX_DEG];
+            for (int32_t t = 0; t < T; ++t) {
+                int ok = 1;
+                int32_t n = or_predecessors(I, b, nb);
+                for (int32_t k = 0; k < n; ++k)
+                    if (p[nb[k]] > t) ok = 0;
+                n = or_successors(I, b, nb);
+                for (int32_t k = 0; k < n; ++k)
+                    if (t > p[nb[k]]) ok = 0;
+                if (!(M[t] + ton <= I->mcap)) ok = 0;
+                for (int32_t s = 0; s < S && ok; ++s)
+                    if (ore(I, s, b) && !(O[(int64_t)s * T + t] + ton <= I->pcap)) ok = 0;
+                if (!ok) continue;
+                p[b] = (int8_t)t;
+                M[t] += ton;
+                for (int32_t s = 0; s < S; ++s)
+                    if (ore(I, s, b)) O[(int64_t)s * T + t] += ton;
+                ++now;
+                break;
+            }
+        }
+        placed += now;
+        if (now == 0) break;
+    }
+    if (n_placed) *n_placed = placed;
+    free(ord); free(O); free(M);
+    return passes;
+}
+
+/* ---- cascading repair (Alg. 4 with its fallback) ----------------------------
+ * The greedy repair walk, where a candidate (b, t') that precedence forbids is
+ * not skipped but taken together with the blocks that forbid it: moving b
+ * earlier (t' < p_b) takes along every ancestor a reached through
+ * predecessors with p_a > t', moving it later takes along every descendant c
+ * reached through successors with p_c < t'; the whole set goes to t'.  The
+ * set is found breadth-first (predecessor or successor lists in their order)
+ * and holds b first.  The composite move is scored exactly: every N'_s, mu',
+ * sigma' from scratch, and the hinge terms of every period the set leaves or
+ * enters re-derived.  It is applied iff the set has at most max_set blocks,
+ * none of them was moved earlier in this call, the resulting schedule
+ * satisfies Eq. 15 at every moved block, (with hard_capacity) the mining
+ * tonnage of t' stays within Mcap and the processed tonnage of t' within
+ * Pcap in every scenario, and the score is positive.  A candidate that needs
+ * no companions is exactly the plain repair's move. */
+int32_t or_repair_cascade(const or_inst *I, int8_t *p, int32_t n_cand,
+                          const int32_t *cand_block, const int8_t *cand_period,
+                          int32_t hard_capacity, int32_t max_set, double *J_out,
+                          uint8_t *accepted, int32_t *set_size) {
+    int64_t N = n_blocks(I);
+    int32_t S = I->S, T = I->T;
+    double *d = malloc(sizeof(double) * (T + 1));
+    double *Ns = malloc(sizeof(double) * S);
+    double *Np = malloc(sizeof(double) * S);
+    double *O = malloc(sizeof(double) * S * T);
+    double *Op = malloc(sizeof(double) * S * T);
+    double *M = malloc(sizeof(double) * T);
+    double *Mp = malloc(sizeof(double) * T);
+    uint8_t *moved = calloc((size_t)N, 1);
+    uint8_t *inset = calloc((size_t)N, 1);
+    int32_t *set = malloc(sizeof(int32_t) * (N > 0 ? N : 1));
+    or_discount(T, I->rate, d);
+    or_objective_t obj;
+    or_objective(I, p, &obj, Ns, O, M);
+    int32_t applied = 0;
+    for (int32_t i = 0; i < n_cand; ++i) {
+        int32_t b = cand_block[i], t = cand_period[i];
+        if (accepted) accepted[i] = 0;
+        if (set_size) set_size[i] = 0;
+        if (b < 0 || b >= N || t < 0 || t > T) continue;
+        if (moved[b] || t == p[b]) continue;
+        /* the set: b, then breadth-first the blocks that must move with it */
+        int32_t n = 0, too_big = 0;
+        set[n++] = b;
+        inset[b] = 1;
+        int earlier = t < p[b];
+        for (int32_t q = 0; q < n && !too_big; ++q) {
+            int32_t nb[OR_MAX_DEG];
+            int32_t k = earlier ? or_predecessors(I, set[q], nb) : or_successors(I, set[q], nb);
+            for (int32_t j = 0; j < k; ++j) {
+                int32_t a = nb[j];
+                if (inset[a]) continue;
+                if (earlier ? p[a] > t : p[a] < t) {
+                    if (n == max_set) { too_big = 1; break; }
+                    set[n++] = a;
+                    inset[a] = 1;
+                }
+            }
+        }
+        if (set_size) set_size[i] = too_big ? -1 : n;
+        int ok = !too_big;
+        for (int32_t q = 0; q < n && ok; ++q)
+            if (moved[set[q]]) ok = 0;
+        /* Eq. 15 at every moved block of the composite schedule */
+        for (int32_t q = 0; q < n && ok; ++q) {
+            int32_t x = set[q], nb[OR_MAX_DEG];
+            int32_t k = or_predecessors(I, x, nb);
+            for (int32_t j = 0; j < k; ++j)
+                if ((inset[nb[j]] ? t : p[nb[j]]) > t) ok = 0;
+            k = or_successors(I, x, nb);
+            for (int32_t j = 0; j < k; ++j)
+                if (t > (inset[nb[j]] ? t : p[nb[j]])) ok = 0;
+        }
+        double score = 0.0;
+        if (ok) {
+            /* N'_s from scratch: N_s plus every moved block's change */
+            for (int32_t s = 0; s < S; ++s) {
+                double acc = Ns[s];
+                for (int32_t q = 0; q < n; ++q)
+                    acc += val(I, s, set[q]) * (wdisc(I, d, s, t) - wdisc(I, d, s, p[set[q]]));
+                Np[s] = acc;
+            }
+            double mu, sd, mu2, sd2;
+            mean_std(Ns, S, &mu, &sd);
+            mean_std(Np, S, &mu2, &sd2);
+            double dR = risk_value(I, Np, mu2, sd2) - risk_value(I, Ns, mu, sd);
+            /* tonnages after the move, then the hinge terms of every period */
+            memcpy(Op, O, sizeof(double) * S * T);
+            memcpy(Mp, M, sizeof(double) * T);
+            for (int32_t q = 0; q < n; ++q) {
+                int32_t x = set[q], u = p[x];
+                double ton = I->ton[x];
+                if (u < T) Mp[u] -= ton;
+                if (t < T) Mp[t] += ton;
+                for (int32_t s = 0; s < S; ++s) {
+                    if (!ore(I, s, x)) continue;
+                    if (u < T) Op[(int64_t)s * T + u] -= ton;
+                    if (t < T) Op[(int64_t)s * T + t] += ton;
+                }
+            }
+            double acc = 0.0, am = 0.0;
+            for (int32_t u = 0; u < T; ++u) {
+                int touched = (u == t);
+                for (int32_t q = 0; q < n && !touched; ++q)
+                    if (p[set[q]] == u) touched = 1;
+                if (!touched) continue;
+                for (int32_t s = 0; s < S; ++s)
+                    acc += hinge(Op[(int64_t)s * T + u], I->pcap) -
+                           hinge(O[(int64_t)s * T + u], I->pcap);
+                am += hinge(Mp[u], I->mcap) - hinge(M[u], I->mcap);
+            }
+            double dPp = I->pen_proc * acc / S, dPm = I->pen_mine * am;
+            score = dR - dPp - dPm;
+            if (hard_capacity && t < T) {
+                if (!(Mp[t] <= I->mcap)) ok = 0;
+                for (int32_t s = 0; s < S && ok; ++s)
+                    if (!(Op[(int64_t)s * T + t] <= I->pcap)) ok = 0;
+            }
+        }
+        if (ok && score > 0.0) {
+            memcpy(Ns, Np, sizeof(double) * S);
+            memcpy(O, Op, sizeof(double) * S * T);
+            memcpy(M, Mp, sizeof(double) * T);
+            for (int32_t q = 0; q < n; ++q) {
+                p[set[q]] = (int8_t)t;
+                moved[set[q]] = 1;
+            }
+            if (accepted) accepted[i] = 1;
+            ++applied;
+        }
+        for (int32_t q = 0; q < n; ++q) inset[set[q]] = 0;
+    }
+    if (J_out) {
+        or_objective(I, p, &obj, NULL, NULL, NULL);
+        *J_out = obj.J;
+    }
+    free(d); free(Ns); free(Np); free(O); free(Op); free(M); free(Mp);
+    free(moved); free(inset); free(set);
+    return applied;
+}
+
+/* ---- LNS + simulated annealing driver (Alg. 2 without its GA and RL parts) --
+ * Neighbourhoods: the x-y tiles of nb x nb block columns (every bench), in
+ * row-major tile order.  One step on neighbourhood i at iteration it:
+ *   destroy: the region = the tile's blocks and every descendant of them
+ *     (through successor lists) is set to "never" (the result stays
+ *     precedence-feasible: a block outside the region has no predecessor in
+ *     it);
+ *   repair: up to max_rounds rounds of {evaluate every move (b, t), b in the
+ *     region by increasing index, t = 0..T-1 in order; take the top k by
+ *     score (PREC_OK required, NOOP and BAD forbidden); greedy repair with
+ *     them}, stopping after a round that applies nothing;
+ *   fitness with the eps-relaxed constraints: the capacity violation of a
+ *     schedule is its penalty P = Pp + Pm, and f(S) = R(S) - max(0, P(S) - eps)
+ *     with eps = eps_max (1 - it / n_iter), decreasing linearly (at eps = 0,
+ *     f = J);
+ *   simulated-annealing transition: the candidate replaces the current
+ *     schedule iff f(cand) > f(cur) - u temp, u the step's uniform draw in
+ *     [0,1) (given), temp the temperature of the iteration (temp0 times
+ *     cool^it); otherwise the current schedule is kept.
+ * The best schedule by J (eps = 0) over the run, starting with the input, is
+ * returned in p.  traj (may be NULL) receives per step: J, R, P of the
+ * candidate, and 1/0 for accepted.  stats: steps, accepted, moves evaluated,
+ * moves applied. */
+static void region_of_tile(const or_inst *I, int32_t tx, int32_t ty, int32_t nb,
+                           uint8_t *reg) {
+    int64_t N = n_blocks(I);
+    for (int64_t b = 0; b < N; ++b) {
+        int32_t x = (int32_t)(b % I->nx), y = (int32_t)((b / I->nx) % I->ny);
+        reg[b] = (x / nb == tx && y / nb == ty) ? 1 : 0;
+    }
+    int changed = 1;
+    while (changed) {   /* descendants: a block with a predecessor in the region */
+        changed = 0;
+        for (int64_t c = 0; c < N; ++c) {
+            if (reg[c]) continue;
+            int32_t pr[OR_MAX_DEG];
+            int32_t np = or_predecessors(I, (int32_t)c, pr);
+            for (int32_t k = 0; k < np; ++k)
+                if (reg[pr[k]]) {
+                    reg[c] = 1;
+                    changed = 1;
+                    break;
+                }
+        }
+    }
+}
+
+double or_lns_sa(const or_inst *I, int8_t *p, int32_t n_iter, int32_t nb, int32_t k,
+                 int32_t max_rounds, double eps_max, double temp0, double cool,
+                 const double *u, double *traj, int64_t *stats, int32_t n_threads) {
+    int64_t N = n_blocks(I);
+    int32_t T = I->T;
+    int32_t kx = (I->nx + nb - 1) / nb, ky = (I->ny + nb - 1) / nb, K = kx * ky;
+    int8_t *cur = malloc((size_t)N), *cand = malloc((size_t)N), *best = malloc((size_t)N);
+    uint8_t *reg = malloc((size_t)N);
+    int32_t *lb = malloc(sizeof(int32_t) * N * T > 0 ? sizeof(int32_t) * N * T : 4);
+    int8_t *lt = malloc((size_t)N * T > 0 ? (size_t)N * T : 1);
+    double *sc = malloc(sizeof(double) * (N * T > 0 ? N * T : 1));
+    uint8_t *fl = malloc((size_t)(N * T > 0 ? N * T : 1));
+    int64_t *idx = malloc(sizeof(int64_t) * k);
+    int32_t *cb = malloc(sizeof(int32_t) * k);
+    int8_t *ct = malloc((size_t)k);
+    memcpy(cur, p, (size_t)N);
+    memcpy(best, p, (size_t)N);
+    or_objective_t o;
+    or_objective(I, cur, &o, NULL, NULL, NULL);
+    double J_best = o.J;
+    double R_cur = o.R, P_cur = o.Pp + o.Pm;
+    int64_t steps = 0, acc_n = 0, n_eval = 0, n_app = 0;
+    for (int32_t it = 0; it < n_iter; ++it) {
+        double eps = eps_max * (1.0 - (double)it / n_iter);
+        double temp = temp0;
+        for (int32_t j = 0; j < it; ++j) temp *= cool;
+        for (int32_t i = 0; i < K; ++i) {
+            region_of_tile(I, i % kx, i / kx, nb, reg);
+            memcpy(cand, cur, (size_t)N);
+            int64_t m = 0;
+            for (int64_t b = 0; b < N; ++b) {
+                if (!reg[b]) continue;
+                cand[b] = (int8_t)T;
+                for (int32_t t = 0; t < T; ++t) {
+                    lb[m] = (int32_t)b;
+                    lt[m] = (int8_t)t;
+                    ++m;
+                }
+            }
+            for (int32_t r = 0; r < max_rounds; ++r) {
+                or_eval_moves(I, cand, 0, 1, m, lb, lt, sc, fl, NULL, NULL, NULL, n_threads);
+                n_eval += m;
+                int32_t c = or_topk(sc, fl, m, k, OR_PREC_OK, OR_NOOP | OR_BAD, idx, NULL);
+                for (int32_t q = 0; q < c; ++q) {
+                    cb[q] = lb[idx[q]];
+                    ct[q] = lt[idx[q]];
+                }
+                int32_t a = or_repair(I, cand, c, cb, ct, 0, NULL, NULL);
+                n_app += a;
+                if (a == 0) break;
+            }
+            or_objective(I, cand, &o, NULL, NULL, NULL);
+            double P_cand = o.Pp + o.Pm;
+            double f_cand = o.R - (P_cand - eps > 0.0 ? P_cand - eps : 0.0);
+            double f_cur = R_cur - (P_cur - eps > 0.0 ? P_cur - eps : 0.0);
+            double uu = u[(int64_t)it * K + i];
+            int accept = f_cand > f_cur - uu * temp;
+            if (traj) {
+                traj[steps * 4 + 0] = o.J;
+                traj[steps * 4 + 1] = o.R;
+                traj[steps * 4 + 2] = P_cand;
+                traj[steps * 4 + 3] = accept ? 1.0 : 0.0;
+            }
+            ++steps;
+            if (accept) {
+                memcpy(cur, cand, (size_t)N);
+                R_cur = o.R;
+                P_cur = P_cand;
+                ++acc_n;
+                if (o.J > J_best) {
+                    J_best = o.J;
+                    memcpy(best, cand, (size_t)N);
+                }
+            }
+        }
+    }
+    memcpy(p, best, (size_t)N);
+    if (stats) {
+        stats[0] = steps;
+        stats[1] = acc_n;
+        stats[2] = n_eval;
+        stats[3] = n_app;
+    }
+    free(cur); free(cand); free(best); free(reg); free(lb); free(lt); free(sc); free(fl);
+    free(idx); free(cb); free(ct);
+    return J_best;
 }

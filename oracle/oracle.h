@@ -38,6 +38,14 @@ typedef struct {
      * or_successor_csr).  All four NULL: the 1-5 slope stencil of the grid.
      * At most OR_MAX_DEG of each per block. */
     const int32_t *pred_ptr, *pred_idx, *succ_ptr, *succ_idx;
+    /* Objective variants.  mult [S][T] (NULL: all 1) multiplies the value of
+     * a block mined in period t under scenario s (Eq. 12's sigma(s,t)).
+     * risk 0: R = mu - lambda*sigma; risk 1: R = mu - lambda*(mu - CVaR),
+     * CVaR the mean of the worst alpha share of the scenario NPVs (lower
+     * tail, fractional weight on the boundary scenario). */
+    const double *mult;
+    int32_t risk;
+    double alpha;
 } or_inst;
 
 #define OR_MAX_DEG 9
@@ -60,6 +68,10 @@ int32_t or_successors(const or_inst *I, int32_t b, int32_t *out /* [OR_MAX_DEG] 
  * [pred_ptr[N]]. */
 void or_successor_csr(int64_t N, const int32_t *pred_ptr, const int32_t *pred_idx,
                       int32_t *succ_ptr, int32_t *succ_idx);
+
+/* CVaR of the lower alpha tail of x [n]: with x sorted ascending and
+ * k = ceil(alpha*n), (sum_{i<k-1} x_(i) + (alpha*n - k + 1) x_(k-1)) / (alpha*n). */
+double or_cvar(const double *x, int32_t n, double alpha);
 
 /* Full objective of schedule p.  Ns [S], O [S][T], M [T] may be NULL. */
 void or_objective(const or_inst *I, const int8_t *p, or_objective_t *out,
@@ -88,6 +100,17 @@ int32_t or_repair(const or_inst *I, int8_t *p, int32_t n_cand,
                   const int32_t *cand_block, const int8_t *cand_period,
                   int32_t hard_capacity, double *J_out, uint8_t *accepted);
 
+/* Cascading repair: as or_repair, but a candidate precedence forbids moves
+ * together with the ancestors (moving earlier) or descendants (moving later)
+ * that forbid it, as one composite move to the same period, scored exactly;
+ * sets larger than max_set blocks are skipped.  set_size [n_cand] (may be
+ * NULL) receives each candidate's set size (0: skipped before forming it,
+ * -1: too large). */
+int32_t or_repair_cascade(const or_inst *I, int8_t *p, int32_t n_cand,
+                          const int32_t *cand_block, const int8_t *cand_period,
+                          int32_t hard_capacity, int32_t max_set, double *J_out,
+                          uint8_t *accepted, int32_t *set_size);
+
 /* Relaxed objective of a cumulative schedule x [N][T]; grad (may be NULL)
  * receives dJ/dx [N][T]. */
 double or_relaxed(const or_inst *I, const float *x, const or_relax_t *rp,
@@ -108,6 +131,26 @@ int32_t or_rank_moves(const or_inst *I, const int8_t *p, const double *grad,
 double or_search(const or_inst *I, int8_t *p, int32_t mode, int32_t k,
                  const or_relax_t *rp, int32_t max_iter, int64_t *stats,
                  int32_t n_threads);
+
+/* Greedy initializer (Alg. 3, uncertainty factors 1): p [N] receives the
+ * schedule built by placing blocks in descending expected value at their
+ * earliest period that keeps precedence and both hard capacities, in passes
+ * until a pass places nothing (at most max_pass).  Returns the number of
+ * passes; *n_placed (may be NULL) the number of blocks placed. */
+int32_t or_greedy_init(const or_inst *I, int8_t *p, int32_t max_pass, int64_t *n_placed);
+
+/* LNS + simulated annealing driver (Alg. 2 without GA and RL): n_iter
+ * iterations over the nb x nb column tiles; each step destroys a tile and its
+ * descendants, repairs with up to max_rounds rounds of list evaluation, top k
+ * and greedy repair, and accepts the candidate iff
+ * f(cand) > f(cur) - u temp0 cool^it with f = R - max(0, Pp + Pm - eps),
+ * eps = eps_max (1 - it/n_iter).  u [n_iter * tiles] are the uniform draws.
+ * p receives the best schedule by J; returns its J.  traj [steps][4] (may be
+ * NULL): J, R, P of each candidate and 1/0 accepted; stats [4]: steps,
+ * accepted, moves evaluated, moves applied. */
+double or_lns_sa(const or_inst *I, int8_t *p, int32_t n_iter, int32_t nb, int32_t k,
+                 int32_t max_rounds, double eps_max, double temp0, double cool,
+                 const double *u, double *traj, int64_t *stats, int32_t n_threads);
 
 /* Exhaustive optimum over every precedence-feasible schedule (tiny grids).
  * Returns J*; p_best gets the lexicographically smallest maximiser;
