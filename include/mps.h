@@ -4,9 +4,10 @@
  *   N = nx*ny*nz blocks, block index b = x + nx*(y + ny*z), z = 0 the top bench;
  *   a schedule p[b] in {0..T-1} is the period in which block b is mined, and
  *   p[b] = T means "never mined";
- *   precedence (Eq. 15) under the 1-5 slope stencil: the predecessors of b are
- *   the block right above it and the four blocks sharing a face with that
- *   block (bench z-1, clipped at the grid edges); p[a] <= p[b] for each of them;
+ *   precedence (Eq. 15): p[a] <= p[b] for each predecessor a of b; by default
+ *   the 1-5 slope stencil (the block right above b and the four blocks
+ *   sharing a face with that block, bench z-1, clipped at the grid edges),
+ *   or explicit predecessor lists (MPS_PREC_CSR);
  *   S geological scenarios give block values v[s][b] ($) and ore indicators
  *   ore[s][b] (block processed in scenario s); ton[b] is the block tonnage.
  *
@@ -75,11 +76,21 @@ enum {
 
 typedef struct mps_model mps_model;
 
+/* Precedence of a model (Eq. 15's predecessor sets):
+ *   MPS_PREC_GRID_1_5  the 1-5 slope stencil of the grid (the default);
+ *   MPS_PREC_CSR       explicit predecessor lists given to mps_build_model:
+ *                      the predecessors of b are pred_idx[pred_ptr[b] ..
+ *                      pred_ptr[b+1]), at most MPS_MAX_DEGREE of them, and no
+ *                      block has more than MPS_MAX_DEGREE successors. */
+#define MPS_PREC_GRID_1_5 0
+#define MPS_PREC_CSR 1
+#define MPS_MAX_DEGREE 9
+
 typedef struct {
     int32_t nx, ny, nz;      /* grid; N = nx*ny*nz >= 1 */
     int32_t n_scen;          /* S, 1..MPS_MAX_SCENARIOS */
     int32_t n_periods;       /* T, 1..MPS_MAX_PERIODS; destination T = never */
-    int32_t reserved;        /* must be 0 */
+    int32_t precedence;      /* MPS_PREC_GRID_1_5 or MPS_PREC_CSR */
     double discount_rate;    /* per period, > -1 (0.08 in the paper) */
     double lambda;           /* weight of the std, finite */
     double pen_proc;         /* $ per tonne of processing excess, >= 0 */
@@ -121,13 +132,20 @@ mps_status mps_device_count(int32_t *n);
 /* Build a model from device arrays on the current device (Sec. 5 parameters):
  *   v        float [S][N]     block values, scenario-major;
  *   ore_bits uint32 [ceil(S/32)][N]; scenario s is bit s%32 of word s/32;
- *   ton      double [N]       tonnages, > 0.
+ *   ton      double [N]       tonnages, > 0;
+ *   pred_ptr int32 [N+1], pred_idx int32 [pred_ptr[N]]: HOST arrays, the
+ *            predecessor lists of MPS_PREC_CSR (Eq. 15's sets; each list
+ *            without repeats or b itself, indices in [0,N)); NULL with
+ *            MPS_PREC_GRID_1_5.  The successor lists are derived.
+ * Invalid lists (bad pointers or indices, a repeat, a self loop, more than
+ * MPS_MAX_DEGREE predecessors or successors) return MPS_E_INVALID_ARG.
  * The model copies what it keeps (the caller may free its arrays afterwards),
  * derives per-block statistics, allocates every buffer later calls need, and
  * starts with the schedule "everything in period 0".  Synchronises `stream`.
  * Not capturable. */
 mps_status mps_build_model(const mps_params *prm, const float *v,
                            const uint32_t *ore_bits, const double *ton,
+                           const int32_t *pred_ptr, const int32_t *pred_idx,
                            void *stream, mps_model **out);
 
 /* Free a model and its device memory (synchronises the device). */
@@ -224,6 +242,25 @@ mps_status mps_repair(mps_model *m, const mps_moves *moves,
                       int32_t max_cand, int32_t hard_capacity,
                       int32_t *applied, void *stream);
 
+/* Cascading repair (Alg. 4 with its fallback): as mps_repair, except that a
+ * candidate (b, t') precedence forbids is not skipped but moved together with
+ * the blocks that forbid it -- for t' < p[b] every ancestor reached through
+ * predecessors with p > t', for t' > p[b] every descendant reached through
+ * successors with p < t' -- all set to t' as one composite move.  The
+ * composite is scored exactly (FP64: every N'_s, mu', sigma' and the hinge
+ * terms of every period the set leaves or enters) and applied iff the set
+ * has at most max_set blocks (1..256), none of them was moved earlier in this
+ * call, Eq. 15 holds at every moved block of the result, (hard_capacity) the
+ * mining and processing tonnages of t' stay within their capacities, and the
+ * score is > 0.  A candidate that needs no companions is the plain repair's
+ * move.  *applied (device int32, may be NULL) receives the number of applied
+ * (composite) moves; the state is re-derived from the schedule at the end.
+ * The walk keeps 8*(T*S + 2S + 2T + 1) bytes of state in one workgroup's LDS,
+ * else MPS_E_INVALID_ARG.  Capturable; calls on one model must not overlap. */
+mps_status mps_repair_cascade(mps_model *m, const mps_moves *moves, const int64_t *idx,
+                              const int32_t *count, int32_t max_cand, int32_t hard_capacity,
+                              int32_t max_set, int32_t *applied, void *stream);
+
 /* ---- relaxed, differentiable schedule ------------------------------------
  * x (device float [N][T]) is the cumulative fraction of each block mined by
  * the end of each period, y[b,t] = x[b,t] - x[b,t-1] (x[b,-1] = 0); the caller
@@ -291,6 +328,77 @@ typedef struct {
 
 mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_params *rp,
                       int32_t max_iter, mps_search_stats *out, void *stream);
+
+/* ---- objective variants ---------------------------------------------------
+ * Two variants of the objective, set per model:
+ *   value multiplier (Eq. 12): a block mined in period t is worth
+ *     sigma(s,t) * v[s][b] in scenario s, so N_s = sum_b v[s][b] sigma(s,p_b) d(p_b);
+ *   risk measure: MPS_RISK_STD gives R = mu - lambda*sigma; MPS_RISK_CVAR gives
+ *     R = mu - lambda*(mu - CVaR_alpha(N)), where CVaR_alpha is the mean of the
+ *     lower alpha tail of the scenario NPVs: with them sorted ascending and
+ *     k = ceil(alpha*S), (sum of the k-1 smallest + (alpha*S - k + 1) * the
+ *     k-th smallest) / (alpha*S)  (alpha = 0.1 is the paper's CVaR10).
+ * mult: HOST double [S][T] (read during the call) or NULL for sigma = 1.
+ * The state of the current schedule is re-derived (synchronises; not
+ * capturable).  mps_get_objective, mps_set_schedule and mps_eval_moves then
+ * follow the variant (evaluation: S <= 1024 and 8*T*S + 4*S*(T+1) bytes of
+ * tables in one workgroup's LDS, else MPS_E_INVALID_ARG); every call built
+ * on the base objective's arithmetic (repair, cascading repair, search,
+ * relaxed objective, ranking, greedy initializer, batches) returns
+ * MPS_E_INVALID_ARG while a variant is set.  mult = NULL with MPS_RISK_STD
+ * restores the base objective. */
+#define MPS_RISK_STD 0
+#define MPS_RISK_CVAR 1
+mps_status mps_set_objective_variant(mps_model *m, const double *mult, int32_t risk,
+                                     double cvar_alpha, void *stream);
+
+/* Greedy initializer (Alg. 3 with every uncertainty factor equal to 1):
+ * replaces the model's schedule by the one built greedily from "nothing
+ * mined".  Blocks are taken in descending expected value mean_s v[s][b] (ties:
+ * smaller index); each is placed in the earliest period t < T that keeps the
+ * partial schedule precedence-feasible (every predecessor already placed in t
+ * or earlier; an unplaced block counts as never mined) and both capacities
+ * hard (M[t] + ton_b <= mine_cap; O[s][t] + ton_b <= proc_cap in every
+ * scenario in which b is ore), or stays unplaced (period T).  Passes over the
+ * unplaced blocks, in the same order, repeat until one places nothing or
+ * max_pass passes ran.  *passes and *placed (host, may be NULL) receive the
+ * pass count and the number of placed blocks; the model's state is derived
+ * from the result.  ALLOCATES its workspace and SYNCHRONISES (not
+ * capturable).  The period tonnages are kept on chip: 8*(T*S + T) bytes
+ * must fit one workgroup's LDS, else MPS_E_INVALID_ARG. */
+mps_status mps_greedy_init(mps_model *m, int32_t max_pass, int32_t *passes, int64_t *placed,
+                           void *stream);
+
+/* LNS + simulated-annealing driver (Alg. 2 without its GA and RL parts).
+ * Neighbourhoods are the tile x tile block columns of the grid (every bench),
+ * in row-major tile order; n_tiles = ceil(nx/tile) * ceil(ny/tile).  One step
+ * on neighbourhood i of iteration it:
+ *   destroy: the tile's blocks and every descendant of them go to "never";
+ *   repair: up to max_rounds rounds of { evaluate every move (b, t < T) of the
+ *     destroyed blocks (b ascending, then t), top k (PREC_OK required, NOOP
+ *     and BAD forbidden), greedy repair (mps_repair) }, stopping after a round
+ *     that applies nothing;
+ *   eps-relaxed fitness: f = R - max(0, Pp + Pm - eps), eps = eps_max *
+ *     (1 - it/n_iter) (linear; f = J at eps = 0);
+ *   acceptance: the candidate becomes the current schedule iff
+ *     f(cand) > f(cur) - u[it*n_tiles + i] * temp0 * cool^it.
+ * u: HOST double [n_iter * n_tiles], the caller's uniform draws in [0,1).
+ * traj: HOST double [n_iter * n_tiles][4] or NULL: J, R, Pp + Pm of each
+ * candidate and 1/0 accepted.  The model ends at the best schedule by J seen
+ * (the input included).  ALLOCATES and SYNCHRONISES every step (not
+ * capturable).  Limits as mps_search. */
+typedef struct {
+    int32_t n_iter, tile, k, max_rounds;
+    double eps_max, temp0, cool;
+} mps_lns_params;
+
+typedef struct {
+    int64_t steps, accepted, evaluations, applied;
+    double J_best;
+} mps_lns_stats;
+
+mps_status mps_lns_sa(mps_model *m, const mps_lns_params *prm, const double *u, double *traj,
+                      mps_lns_stats *out, void *stream);
 
 /* ---- batched evaluation ---------------------------------------------------
  * Many models (for instance, one schedule per individual of the population

@@ -10,6 +10,7 @@ import ctypes as C
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -34,7 +35,7 @@ class MpsError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("n_scen", C.c_int32), ("n_periods", C.c_int32),
-                ("reserved", C.c_int32), ("discount_rate", C.c_double),
+                ("precedence", C.c_int32), ("discount_rate", C.c_double),
                 ("lam", C.c_double), ("pen_proc", C.c_double),
                 ("pen_mine", C.c_double), ("proc_cap", C.c_double),
                 ("mine_cap", C.c_double)]
@@ -61,6 +62,17 @@ class SearchStats(C.Structure):
                 ("applied", C.c_int64), ("J", C.c_double)]
 
 
+class LnsParams(C.Structure):
+    _fields_ = [("n_iter", C.c_int32), ("tile", C.c_int32), ("k", C.c_int32),
+                ("max_rounds", C.c_int32), ("eps_max", C.c_double), ("temp0", C.c_double),
+                ("cool", C.c_double)]
+
+
+class LnsStats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("accepted", C.c_int64), ("evaluations", C.c_int64),
+                ("applied", C.c_int64), ("J_best", C.c_double)]
+
+
 class Tuning(C.Structure):
     _fields_ = [("tiles_per_item", C.c_int32), ("moves_per_item", C.c_int32),
                 ("rows", C.c_int32), ("reserved", C.c_int32)]
@@ -82,7 +94,7 @@ def _load():
         "mps_last_error": ([], C.c_char_p),
         "mps_version": ([], i32),
         "mps_device_count": ([vp], st),
-        "mps_build_model": ([vp, vp, vp, vp, vp, vp], st),
+        "mps_build_model": ([vp, vp, vp, vp, vp, vp, vp, vp], st),
         "mps_destroy_model": ([vp], st),
         "mps_model_dims": ([vp, vp, vp, vp], st),
         "mps_set_schedule": ([vp, vp, vp], st),
@@ -95,12 +107,16 @@ def _load():
                       C.c_size_t, vp], st),
         "mps_topk_noalloc": ([vp, vp, i64, i32, C.c_uint8, C.c_uint8, vp, vp, vp, vp], st),
         "mps_repair": ([vp, vp, vp, vp, i32, i32, vp, vp], st),
+        "mps_repair_cascade": ([vp, vp, vp, vp, i32, i32, i32, vp, vp], st),
         "mps_relaxed_saved_bytes": ([vp], C.c_size_t),
         "mps_relaxed_fwd": ([vp, vp, vp, vp, vp, vp], st),
         "mps_relaxed_bwd": ([vp, vp, vp, vp, vp, vp, vp], st),
         "mps_rank_ws_bytes": ([vp, i32], C.c_size_t),
         "mps_rank_moves": ([vp, vp, i32, vp, vp, vp, vp, vp, C.c_size_t, vp], st),
         "mps_search": ([vp, i32, i32, vp, i32, vp, vp], st),
+        "mps_greedy_init": ([vp, i32, vp, vp, vp], st),
+        "mps_lns_sa": ([vp, vp, vp, vp, vp, vp], st),
+        "mps_set_objective_variant": ([vp, vp, i32, C.c_double, vp], st),
         "mps_state_bytes": ([vp], C.c_size_t),
         "mps_state_save": ([vp, vp, vp], st),
         "mps_state_restore": ([vp, vp, vp], st),
@@ -127,8 +143,11 @@ EXPORTS = ("mps_last_error", "mps_version", "mps_device_count", "mps_build_model
            "mps_destroy_model", "mps_model_dims", "mps_set_schedule",
            "mps_get_schedule", "mps_get_objective", "mps_objective_async",
            "mps_eval_moves", "mps_topk_ws_bytes", "mps_topk", "mps_topk_noalloc", "mps_repair",
+           "mps_repair_cascade",
            "mps_relaxed_saved_bytes", "mps_relaxed_fwd", "mps_relaxed_bwd",
-           "mps_rank_ws_bytes", "mps_rank_moves", "mps_search", "mps_state_bytes",
+           "mps_rank_ws_bytes", "mps_rank_moves", "mps_search", "mps_greedy_init",
+           "mps_set_objective_variant", "mps_lns_sa",
+           "mps_state_bytes",
            "mps_state_save", "mps_state_restore", "mps_batch_create", "mps_batch_destroy",
            "mps_batch_set_tuning", "mps_batch_get_tuning", "mps_batch_set_workgroups",
            "mps_batch_run", "mps_batch_graph_launch", "mps_batch_autotune")
@@ -187,26 +206,34 @@ class Model:
     """A block model on the GPU (mps_build_model) with its current schedule."""
 
     def __init__(self, nx, ny, nz, S, T, v, ore_words, ton, *, rate=0.08, lam=0.5,
-                 pen_proc=100.0, pen_mine=100.0, proc_cap, mine_cap, stream=None):
+                 pen_proc=100.0, pen_mine=100.0, proc_cap, mine_cap, pred_ptr=None,
+                 pred_idx=None, stream=None):
         N = nx * ny * nz
         W = (S + 31) // 32
         _dev(v, torch.float32, (S, N), "v")
         _dev(ore_words, torch.int32, (W, N), "ore_words")
         _dev(ton, torch.float64, (N,), "ton")
-        self.prm = Params(nx, ny, nz, S, T, 0, rate, lam, pen_proc, pen_mine,
+        csr = pred_ptr is not None
+        lists = [None, None]
+        if csr:
+            # host arrays, read during the build
+            self._pred = (np.ascontiguousarray(pred_ptr, dtype=np.int32),
+                          np.ascontiguousarray(pred_idx, dtype=np.int32))
+            lists = [a.ctypes.data_as(C.c_void_p) for a in self._pred]
+        self.prm = Params(nx, ny, nz, S, T, 1 if csr else 0, rate, lam, pen_proc, pen_mine,
                           proc_cap, mine_cap)
         self.N, self.S, self.T, self.W = N, S, T, W
         self.device = v.device
         h = C.c_void_p()
         check(lib.mps_build_model(C.byref(self.prm), _ptr(v), _ptr(ore_words),
-                                  _ptr(ton), _stream(stream), C.byref(h)))
+                                  _ptr(ton), lists[0], lists[1], _stream(stream), C.byref(h)))
         self.h = h
         self._objbuf = torch.empty(8, dtype=torch.float64, device=self.device)
 
     @classmethod
     def from_instance(cls, inst, device="cuda", stream=None):
-        """Build from a generated instance (numpy arrays copied to the GPU)."""
-        import numpy as np
+        """Build from a generated instance (numpy arrays copied to the GPU);
+        explicit predecessor lists (pred_ptr, pred_idx) when it carries them."""
         import mpsgen
         v = torch.from_numpy(np.ascontiguousarray(inst.v)).to(device)
         words = mpsgen.ore_pack(inst.ore).view(np.int32)
@@ -214,7 +241,9 @@ class Model:
         ton = torch.from_numpy(np.ascontiguousarray(inst.ton, dtype=np.float64)).to(device)
         m = cls(inst.nx, inst.ny, inst.nz, inst.S, inst.T, v, ore, ton, rate=inst.rate,
                 lam=inst.lam, pen_proc=inst.pen_proc, pen_mine=inst.pen_mine,
-                proc_cap=inst.pcap, mine_cap=inst.mcap, stream=stream)
+                proc_cap=inst.pcap, mine_cap=inst.mcap,
+                pred_ptr=getattr(inst, "pred_ptr", None),
+                pred_idx=getattr(inst, "pred_idx", None), stream=stream)
         p = torch.from_numpy(np.ascontiguousarray(inst.p0, dtype=np.int8)).to(device)
         m.set_schedule(p, stream)
         return m
@@ -296,6 +325,18 @@ class Model:
                              int(bool(hard)), _ptr(applied), _stream(stream)))
         return applied
 
+    def repair_cascade(self, moves: MoveSet, idx, count, max_cand=None, hard=False,
+                       max_set=64, applied=None, stream=None):
+        """Cascading repair (mps_repair_cascade) over the same kind of list."""
+        max_cand = int(idx.shape[0]) if max_cand is None else max_cand
+        if applied is None:
+            applied = torch.zeros(1, dtype=torch.int32, device=self.device)
+        mv = moves.c()
+        check(lib.mps_repair_cascade(self.h, C.byref(mv), _ptr(idx), _ptr(count),
+                                     int(max_cand), int(bool(hard)), int(max_set),
+                                     _ptr(applied), _stream(stream)))
+        return applied
+
 
     # ---- relaxed objective -------------------------------------------------
     def relaxed_saved(self):
@@ -341,6 +382,42 @@ class Model:
                              C.byref(st), _stream(stream)))
         return dict(iterations=st.iterations, evaluations=st.evaluations,
                     applied=st.applied, J=st.J)
+
+    def set_objective_variant(self, mult=None, risk=0, alpha=0.1, stream=None):
+        """Value multiplier sigma(s,t) (host array [S][T] or None) and risk
+        measure (0: std, 1: CVaR of the lower alpha tail); re-derives the
+        state (mps_set_objective_variant)."""
+        ptr = None
+        if mult is not None:
+            mult = np.ascontiguousarray(mult, dtype=np.float64)
+            if mult.shape != (self.S, self.T):
+                raise ValueError(f"mult must have shape {(self.S, self.T)}")
+            ptr = mult.ctypes.data_as(C.c_void_p)
+        check(lib.mps_set_objective_variant(self.h, ptr, int(risk), float(alpha),
+                                            _stream(stream)))
+
+    def lns_sa(self, n_iter, tile, k, max_rounds, eps_max, temp0, cool, u, stream=None):
+        """LNS + SA driver (mps_lns_sa); returns (stats dict, trajectory [steps][4])."""
+        K = ((self.prm.nx + tile - 1) // tile) * ((self.prm.ny + tile - 1) // tile)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        if u.shape != (n_iter * K,):
+            raise ValueError(f"u must hold n_iter * tiles = {n_iter * K} draws")
+        traj = np.zeros((n_iter * K, 4))
+        prm = LnsParams(int(n_iter), int(tile), int(k), int(max_rounds), float(eps_max),
+                        float(temp0), float(cool))
+        st = LnsStats()
+        check(lib.mps_lns_sa(self.h, C.byref(prm), u.ctypes.data_as(C.c_void_p),
+                             traj.ctypes.data_as(C.c_void_p), C.byref(st), _stream(stream)))
+        return dict(steps=st.steps, accepted=st.accepted, evaluations=st.evaluations,
+                    applied=st.applied, J_best=st.J_best), traj
+
+    def greedy_init(self, max_pass=1000, stream=None):
+        """Replace the schedule by the greedy initializer's (mps_greedy_init);
+        returns (passes, placed)."""
+        passes, placed = C.c_int32(0), C.c_int64(0)
+        check(lib.mps_greedy_init(self.h, int(max_pass), C.byref(passes), C.byref(placed),
+                                  _stream(stream)))
+        return passes.value, placed.value
 
 
 class RelaxedNPV(torch.autograd.Function):

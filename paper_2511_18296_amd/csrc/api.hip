@@ -105,6 +105,9 @@ struct mps_model {
     void *relax_ws = nullptr;    // partial sums of the relaxed forward pass
     void *gather = nullptr;      // candidate records of a repair walk
     int32_t *rep_first = nullptr;   // [N] first candidate of each block in a walk; INT32_MAX between calls
+    uint8_t *cmark = nullptr;       // [N] blocks moved in a cascading repair call
+    double *wmult = nullptr;        // [S][T+1] discounted value multipliers (once set)
+    float *wmult32 = nullptr;
     char *arena = nullptr;       // mutable search state (see mps_state_save)
     size_t arena_bytes = 0;
     int max_lds = 65536;
@@ -166,7 +169,9 @@ static mps_status check_params(const mps_params *p) {
     if (p->n_periods < 1 || p->n_periods > MPS_MAX_PERIODS)
         return fail(MPS_E_INVALID_ARG, "n_periods must be in 1..%d (got %d)", MPS_MAX_PERIODS,
                     p->n_periods);
-    if (p->reserved != 0) return fail(MPS_E_INVALID_ARG, "reserved must be 0");
+    if (p->precedence != MPS_PREC_GRID_1_5 && p->precedence != MPS_PREC_CSR)
+        return fail(MPS_E_INVALID_ARG, "precedence must be MPS_PREC_GRID_1_5 or MPS_PREC_CSR (got %d)",
+                    p->precedence);
     if (!isfinite(p->discount_rate) || p->discount_rate <= -1.0)
         return fail(MPS_E_INVALID_ARG, "discount_rate must be finite and > -1");
     if (!isfinite(p->lambda)) return fail(MPS_E_INVALID_ARG, "lambda must be finite");
@@ -177,12 +182,61 @@ static mps_status check_params(const mps_params *p) {
     return MPS_OK;
 }
 
+// Explicit predecessor lists: validated, and their transpose (successor
+// lists, each in increasing block index) built on the host.
+static mps_status check_lists(int64_t N, const int32_t *pred_ptr, const int32_t *pred_idx,
+                              std::vector<int32_t> &sp, std::vector<int32_t> &si) {
+    if (!pred_ptr || !pred_idx)
+        return fail(MPS_E_INVALID_ARG, "MPS_PREC_CSR needs pred_ptr and pred_idx");
+    if (pred_ptr[0] != 0) return fail(MPS_E_INVALID_ARG, "pred_ptr[0] must be 0");
+    for (int64_t b = 0; b < N; ++b) {
+        const int64_t deg = (int64_t)pred_ptr[b + 1] - pred_ptr[b];
+        if (deg < 0 || deg > MPS_MAX_DEGREE)
+            return fail(MPS_E_INVALID_ARG, "block %lld has %lld predecessors (0..%d allowed)",
+                        (long long)b, (long long)deg, MPS_MAX_DEGREE);
+        for (int32_t j = pred_ptr[b]; j < pred_ptr[b + 1]; ++j) {
+            const int32_t a = pred_idx[j];
+            if (a < 0 || a >= N || a == b)
+                return fail(MPS_E_INVALID_ARG, "block %lld: predecessor %d is out of range or "
+                            "the block itself", (long long)b, a);
+            for (int32_t i = pred_ptr[b]; i < j; ++i)
+                if (pred_idx[i] == a)
+                    return fail(MPS_E_INVALID_ARG, "block %lld lists predecessor %d twice",
+                                (long long)b, a);
+        }
+    }
+    const int64_t nnz = pred_ptr[N];
+    sp.assign((size_t)N + 1, 0);
+    si.assign((size_t)(nnz > 0 ? nnz : 1), 0);
+    for (int64_t c = 0; c < N; ++c)
+        for (int32_t j = pred_ptr[c]; j < pred_ptr[c + 1]; ++j) ++sp[(size_t)pred_idx[j] + 1];
+    for (int64_t b = 0; b < N; ++b) {
+        if (sp[b + 1] > MPS_MAX_DEGREE)
+            return fail(MPS_E_INVALID_ARG, "block %lld has %d successors (0..%d allowed)",
+                        (long long)b, sp[b + 1], MPS_MAX_DEGREE);
+        sp[b + 1] += sp[b];
+    }
+    std::vector<int32_t> fill(sp.begin(), sp.end() - 1);
+    for (int64_t c = 0; c < N; ++c)
+        for (int32_t j = pred_ptr[c]; j < pred_ptr[c + 1]; ++j)
+            si[(size_t)fill[pred_idx[j]]++] = (int32_t)c;
+    return MPS_OK;
+}
+
 mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t *ore_bits,
-                           const double *ton, void *stream, mps_model **out) {
+                           const double *ton, const int32_t *pred_ptr, const int32_t *pred_idx,
+                           void *stream, mps_model **out) {
     if (!out) return fail(MPS_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
     mps_status st = check_params(prm);
     if (st != MPS_OK) return st;
+    std::vector<int32_t> succ_ptr, succ_idx;
+    if (prm->precedence == MPS_PREC_CSR) {
+        const int64_t Nl = (int64_t)prm->nx * prm->ny * prm->nz;
+        if ((st = check_lists(Nl, pred_ptr, pred_idx, succ_ptr, succ_idx)) != MPS_OK) return st;
+    } else if (pred_ptr || pred_idx) {
+        return fail(MPS_E_INVALID_ARG, "predecessor lists are given only with MPS_PREC_CSR");
+    }
     if (!v || !ore_bits || !ton) return fail(MPS_E_INVALID_ARG, "v, ore_bits and ton are required");
     int32_t ndev = 0;
     if ((st = mps_device_count(&ndev)) != MPS_OK) return st;
@@ -310,6 +364,31 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
         ALLOC(gw, repair_gather_bytes(S, W));
         m->gather = gw;
         ALLOC(m->rep_first, N);
+        ALLOC(m->cmark, N);
+    }
+    if (prm->precedence == MPS_PREC_CSR) {
+        const size_t nnz = (size_t)pred_ptr[N];
+        int32_t *pp_ = nullptr, *pi_ = nullptr, *sp_ = nullptr, *si_ = nullptr;
+        ALLOC(pp_, (size_t)N + 1);
+        ALLOC(pi_, nnz);
+        ALLOC(sp_, (size_t)N + 1);
+        ALLOC(si_, nnz);
+        hipError_t ce = hipMemcpy(pp_, pred_ptr, 4 * ((size_t)N + 1), hipMemcpyHostToDevice);
+        if (ce == hipSuccess && nnz) ce = hipMemcpy(pi_, pred_idx, 4 * nnz, hipMemcpyHostToDevice);
+        if (ce == hipSuccess)
+            ce = hipMemcpy(sp_, succ_ptr.data(), 4 * ((size_t)N + 1), hipMemcpyHostToDevice);
+        if (ce == hipSuccess && nnz)
+            ce = hipMemcpy(si_, succ_idx.data(), 4 * nnz, hipMemcpyHostToDevice);
+        if (ce != hipSuccess) {
+            m->release();
+            delete m;
+            return dev_fail(ce, "copy of the predecessor lists");
+        }
+        d.csr = 1;
+        d.pred_ptr = pp_;
+        d.pred_idx = pi_;
+        d.succ_ptr = sp_;
+        d.succ_idx = si_;
     }
 #undef ALLOC
     d.v = v_;
@@ -471,7 +550,29 @@ static mps_status check_moves(const mps_model *m, const mps_moves *mv) {
 
 // The evaluation kernels keep one tile's tables in LDS: S and T together must
 // leave them room.
+// Calls whose arithmetic is the base objective's refuse a model with an
+// objective variant.
+static mps_status no_variant(const mps_model *m, const char *what) {
+    if (has_variant(m->d))
+        return fail(MPS_E_INVALID_ARG,
+                    "%s uses the base objective (std risk, no value multiplier); this model "
+                    "has an objective variant set", what);
+    return MPS_OK;
+}
+
 static mps_status check_eval_lds(const mps_model *m, const mps_moves &mv) {
+    if (has_variant(m->d)) {
+        if (m->d.S > kVariantMaxScen)
+            return fail(MPS_E_INVALID_ARG,
+                        "evaluation under an objective variant supports S <= %d (got %d)",
+                        kVariantMaxScen, m->d.S);
+        const size_t need = eval_var_lds_bytes(m->d);
+        if (need > (size_t)m->max_lds)
+            return fail(MPS_E_INVALID_ARG,
+                        "evaluation under an objective variant keeps 8*T*S + 4*S*(T+1) bytes "
+                        "of tables in LDS (%zu), device allows %d", need, m->max_lds);
+        return MPS_OK;
+    }
     const size_t need = eval_lds_bytes(m->d, mv);
     if (need > (size_t)m->max_lds)
         return fail(MPS_E_INVALID_ARG,
@@ -529,6 +630,7 @@ mps_status mps_repair(mps_model *m, const mps_moves *moves, const int64_t *idx,
     if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
     mps_status st = check_moves(m, moves);
     if (st != MPS_OK) return st;
+    if ((st = no_variant(m, "mps_repair")) != MPS_OK) return st;
     if (!idx || !count) return fail(MPS_E_INVALID_ARG, "idx and count are required");
     if (max_cand < 0 || max_cand > MPS_MAX_TOPK)
         return fail(MPS_E_INVALID_ARG, "max_cand must be in 0..%d", MPS_MAX_TOPK);
@@ -544,6 +646,30 @@ mps_status mps_repair(mps_model *m, const mps_moves *moves, const int64_t *idx,
     hipError_t e = launch_repair(m->d, *moves, idx, count, max_cand, hard_capacity, applied,
                                  m->gather, m->rep_first, (hipStream_t)stream);
     return e == hipSuccess ? MPS_OK : dev_fail(e, "repair");
+}
+
+mps_status mps_repair_cascade(mps_model *m, const mps_moves *moves, const int64_t *idx,
+                              const int32_t *count, int32_t max_cand, int32_t hard_capacity,
+                              int32_t max_set, int32_t *applied, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    mps_status st = check_moves(m, moves);
+    if (st != MPS_OK) return st;
+    if ((st = no_variant(m, "mps_repair_cascade")) != MPS_OK) return st;
+    if (!idx || !count) return fail(MPS_E_INVALID_ARG, "idx and count are required");
+    if (max_cand < 0 || max_cand > MPS_MAX_TOPK)
+        return fail(MPS_E_INVALID_ARG, "max_cand must be in 0..%d", MPS_MAX_TOPK);
+    if (max_set < 1 || max_set > kCascadeMaxSet)
+        return fail(MPS_E_INVALID_ARG, "max_set must be in 1..%d (got %d)", kCascadeMaxSet,
+                    max_set);
+    const size_t need = cascade_lds_bytes(m->d);
+    if (need > (size_t)m->max_lds)
+        return fail(MPS_E_INVALID_ARG,
+                    "cascading repair keeps 8*(T*S + 2S + 2T + 1) bytes of state in LDS "
+                    "(%zu with its set lists); the device allows %d", need, m->max_lds);
+    DeviceGuard g(m->device);
+    hipError_t e = launch_cascade(m->d, *moves, idx, count, max_cand, hard_capacity, max_set,
+                                  applied, m->cmark, m->partial, m->chunks, (hipStream_t)stream);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "cascading repair");
 }
 
 size_t mps_state_bytes(const mps_model *m) { return m ? m->arena_bytes : 0; }
@@ -583,6 +709,7 @@ mps_status mps_relaxed_fwd(mps_model *m, const float *x, const mps_relax_params 
     if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
     mps_status st = check_relax(rp);
     if (st != MPS_OK) return st;
+    if ((st = no_variant(m, "mps_relaxed_fwd")) != MPS_OK) return st;
     if (!x || !saved) return fail(MPS_E_INVALID_ARG, "x and saved are required");
     DeviceGuard g(m->device);
     hipError_t e = launch_relaxed_fwd(m->d, x, *rp, J_out, saved, m->relax_ws, (hipStream_t)stream);
@@ -594,6 +721,7 @@ mps_status mps_relaxed_bwd(mps_model *m, const float *x, const mps_relax_params 
     if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
     mps_status st = check_relax(rp);
     if (st != MPS_OK) return st;
+    if ((st = no_variant(m, "mps_relaxed_bwd")) != MPS_OK) return st;
     if (!x || !saved || !grad_x) return fail(MPS_E_INVALID_ARG, "x, saved and grad_x are required");
     DeviceGuard g(m->device);
     hipError_t e = launch_relaxed_bwd(m->d, x, *rp, saved, dJ, grad_x, m->relax_ws, (hipStream_t)stream);
@@ -614,6 +742,10 @@ mps_status mps_rank_moves(mps_model *m, const float *grad_x, int32_t k, int32_t 
         return fail(MPS_E_INVALID_ARG, "k must be in 1..%d (got %d)", MPS_MAX_TOPK, k);
     if (!grad_x || !block || !period || !count || !ws)
         return fail(MPS_E_INVALID_ARG, "grad_x, block, period, count and ws are required");
+    {
+        const mps_status vs = no_variant(m, "mps_rank_moves");
+        if (vs != MPS_OK) return vs;
+    }
     if (m->d.N * (int64_t)(m->d.T + 1) >= ((int64_t)1 << 31))
         return fail(MPS_E_INVALID_ARG, "too many moves to rank");
     if (ws_bytes < rank_ws_bytes(m->d, k))
@@ -624,9 +756,239 @@ mps_status mps_rank_moves(mps_model *m, const float *grad_x, int32_t k, int32_t 
     return e == hipSuccess ? MPS_OK : dev_fail(e, "rank moves");
 }
 
+mps_status mps_set_objective_variant(mps_model *m, const double *mult, int32_t risk,
+                                     double cvar_alpha, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    if (risk != MPS_RISK_STD && risk != MPS_RISK_CVAR)
+        return fail(MPS_E_INVALID_ARG, "risk must be MPS_RISK_STD or MPS_RISK_CVAR (got %d)", risk);
+    if (risk == MPS_RISK_CVAR && !(cvar_alpha > 0.0 && cvar_alpha <= 1.0))
+        return fail(MPS_E_INVALID_ARG, "cvar_alpha must be in (0, 1] (got %g)", cvar_alpha);
+    hipStream_t hs = (hipStream_t)stream;
+    if (capturing(hs)) return fail(MPS_E_NOT_CAPTURABLE, "mps_set_objective_variant during capture");
+    DevModel &d = m->d;
+    const int32_t S = d.S, T = d.T, T1 = d.T + 1;
+    if (mult) {
+        for (int64_t i = 0; i < (int64_t)S * T; ++i)
+            if (!isfinite(mult[i]))
+                return fail(MPS_E_INVALID_ARG, "mult[%lld] = %g is not finite", (long long)i,
+                            mult[i]);
+    }
+    DeviceGuard g(m->device);
+    mps_status st;
+    if (mult && !m->wmult) {
+        double *w64 = nullptr;
+        float *w32 = nullptr;
+        if ((st = m->alloc(w64, (size_t)S * T1)) != MPS_OK) return st;
+        if ((st = m->alloc(w32, (size_t)S * T1)) != MPS_OK) return st;
+        m->wmult = w64;
+        m->wmult32 = w32;
+    }
+    hipError_t e = hipSuccess;
+    if (mult) {
+        // w[s][t] = d(t) sigma(s,t) in FP64 on the host, d(T) = 0
+        std::vector<double> dh(T1), w(S * (size_t)T1);
+        std::vector<float> w32(S * (size_t)T1);
+        e = hipMemcpy(dh.data(), d.d64, sizeof(double) * T1, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return dev_fail(e, "discount table");
+        for (int32_t s = 0; s < S; ++s)
+            for (int32_t t = 0; t < T1; ++t) {
+                const double x = t < T ? dh[t] * mult[(size_t)s * T + t] : 0.0;
+                w[(size_t)s * T1 + t] = x;
+                w32[(size_t)s * T1 + t] = (float)x;
+            }
+        e = hipMemcpyAsync(m->wmult, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, hs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(m->wmult32, w32.data(), sizeof(float) * w32.size(),
+                               hipMemcpyHostToDevice, hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+        if (e != hipSuccess) return dev_fail(e, "multiplier table");
+    }
+    d.wmult = mult ? m->wmult : nullptr;
+    d.wmult32 = mult ? m->wmult32 : nullptr;
+    d.risk = risk;
+    d.alpha = risk == MPS_RISK_CVAR ? cvar_alpha : 0.0;
+    // the state of the current schedule under the new objective
+    e = launch_set_schedule(d, d.p, m->partial, m->chunks, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    return e == hipSuccess ? MPS_OK : dev_fail(e, "objective variant");
+}
+
+mps_status mps_lns_sa(mps_model *m, const mps_lns_params *prm, const double *u, double *traj,
+                      mps_lns_stats *out, void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    if (!prm || !u) return fail(MPS_E_INVALID_ARG, "params and u are required");
+    {
+        const mps_status vs = no_variant(m, "mps_lns_sa");
+        if (vs != MPS_OK) return vs;
+    }
+    const mps_lns_params P = *prm;
+    if (P.n_iter < 0 || P.tile < 1 || P.k < 1 || P.k > MPS_MAX_TOPK || P.max_rounds < 0)
+        return fail(MPS_E_INVALID_ARG,
+                    "need n_iter >= 0, tile >= 1, 1 <= k <= %d, max_rounds >= 0", MPS_MAX_TOPK);
+    if (!isfinite(P.eps_max) || !isfinite(P.temp0) || !isfinite(P.cool) || P.eps_max < 0 ||
+        P.temp0 < 0 || P.cool < 0)
+        return fail(MPS_E_INVALID_ARG, "eps_max, temp0 and cool must be finite and >= 0");
+    hipStream_t hs = (hipStream_t)stream;
+    if (capturing(hs)) return fail(MPS_E_NOT_CAPTURABLE, "mps_lns_sa during capture");
+    const DevModel &d = m->d;
+    if (d.N * (int64_t)d.T >= ((int64_t)1 << 31)) return fail(MPS_E_INVALID_ARG, "too many moves");
+    if (d.S > kRepairMaxScen)
+        return fail(MPS_E_INVALID_ARG, "repair supports S <= %d (got %d)", kRepairMaxScen, d.S);
+    if (repair_lds_bytes(d, P.k) > (size_t)m->max_lds)
+        return fail(MPS_E_INVALID_ARG, "repair state does not fit in LDS");
+    mps_status st;
+    {
+        mps_moves lst{};
+        if ((st = check_eval_lds(m, lst)) != MPS_OK) return st;
+    }
+    const int32_t kx = (d.nx + P.tile - 1) / P.tile, ky = (d.ny + P.tile - 1) / P.tile;
+    const int32_t K = kx * ky;
+    DeviceGuard g(m->device);
+    SearchBufs B;
+    const int64_t nm = d.N * (int64_t)d.T;
+    char *cur = B.get<char>(m->arena_bytes), *best = B.get<char>(m->arena_bytes);
+    uint8_t *reg = B.get<uint8_t>(d.N);
+    int32_t *lb = B.get<int32_t>(nm);
+    int8_t *lt = B.get<int8_t>(nm);
+    float *score = B.get<float>(nm);
+    uint8_t *flags = B.get<uint8_t>(nm);
+    char *tws = B.get<char>(topk_ws_bytes(nm, P.k));
+    int64_t *idx = B.get<int64_t>(P.k);
+    int32_t *cnt = B.get<int32_t>(4);   // [0] list length, [1] top-k count, [2] applied
+    double *objd = B.get<double>(8);
+    if (!cur || !best || !reg || !lb || !lt || !score || !flags || !tws || !idx || !cnt || !objd)
+        return fail(MPS_E_OUT_OF_MEMORY, "LNS buffers");
+    hipError_t e = hipSuccess;
+    auto objective = [&](double o[7]) {
+        if (e == hipSuccess) e = launch_objective_copy(d, objd, hs);
+        if (e == hipSuccess) e = hipMemcpyAsync(o, objd, 7 * sizeof(double), hipMemcpyDeviceToHost, hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    };
+    auto read_int = [&](const int32_t *src, int32_t &v) {
+        if (e == hipSuccess) e = hipMemcpyAsync(&v, src, sizeof(int32_t), hipMemcpyDeviceToHost, hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    };
+    e = hipMemcpyAsync(cur, m->arena, m->arena_bytes, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(best, m->arena, m->arena_bytes, hipMemcpyDeviceToDevice, hs);
+    double o[7];
+    objective(o);
+    double J_best = o[5], R_cur = o[2], P_cur = o[3] + o[4];
+    int64_t steps = 0, n_acc = 0, n_eval = 0, n_app = 0;
+    for (int32_t it = 0; it < P.n_iter && e == hipSuccess; ++it) {
+        const double eps = P.eps_max * (1.0 - (double)it / P.n_iter);
+        double temp = P.temp0;
+        for (int32_t j = 0; j < it; ++j) temp *= P.cool;
+        for (int32_t i = 0; i < K && e == hipSuccess; ++i) {
+            // the current schedule, its tile destroyed, the state re-derived
+            e = hipMemcpyAsync(m->arena, cur, m->arena_bytes, hipMemcpyDeviceToDevice, hs);
+            const int32_t tx = i % kx, ty = i / kx;
+            if (e == hipSuccess)
+                e = launch_lns_destroy(d, tx * P.tile, std::min(d.nx, (tx + 1) * P.tile),
+                                       ty * P.tile, std::min(d.ny, (ty + 1) * P.tile), reg, lb,
+                                       lt, cnt, hs);
+            if (e == hipSuccess) e = launch_set_schedule(d, d.p, m->partial, m->chunks, hs);
+            int32_t nl = 0;
+            read_int(cnt, nl);
+            mps_moves lst{};
+            lst.exhaustive = 0;
+            lst.include_never = 1;
+            lst.n = nl;
+            lst.block = lb;
+            lst.period = lt;
+            for (int32_t r = 0; r < P.max_rounds && e == hipSuccess && nl > 0; ++r) {
+                e = launch_eval(d, lst, score, flags, nullptr, nullptr, nullptr, hs);
+                if (e == hipSuccess)
+                    e = launch_topk(score, flags, nl, P.k, MPS_PREC_OK, MPS_NOOP | MPS_BAD, idx,
+                                    nullptr, cnt + 1, tws, hs);
+                if (e == hipSuccess)
+                    e = launch_repair(d, lst, idx, cnt + 1, P.k, 0, cnt + 2, m->gather,
+                                      m->rep_first, hs);
+                n_eval += nl;
+                int32_t a = 0;
+                read_int(cnt + 2, a);
+                n_app += a;
+                if (a == 0) break;
+            }
+            objective(o);
+            if (e != hipSuccess) break;
+            const double Pc = o[3] + o[4];
+            const double f_cand = o[2] - (Pc - eps > 0.0 ? Pc - eps : 0.0);
+            const double f_cur = R_cur - (P_cur - eps > 0.0 ? P_cur - eps : 0.0);
+            const bool accept = f_cand > f_cur - u[(int64_t)it * K + i] * temp;
+            if (traj) {
+                traj[steps * 4 + 0] = o[5];
+                traj[steps * 4 + 1] = o[2];
+                traj[steps * 4 + 2] = Pc;
+                traj[steps * 4 + 3] = accept ? 1.0 : 0.0;
+            }
+            ++steps;
+            if (accept) {
+                e = hipMemcpyAsync(cur, m->arena, m->arena_bytes, hipMemcpyDeviceToDevice, hs);
+                R_cur = o[2];
+                P_cur = Pc;
+                ++n_acc;
+                if (o[5] > J_best && e == hipSuccess) {
+                    J_best = o[5];
+                    e = hipMemcpyAsync(best, m->arena, m->arena_bytes, hipMemcpyDeviceToDevice, hs);
+                }
+            }
+        }
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(m->arena, best, m->arena_bytes, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return dev_fail(e, "LNS driver");
+    if (out) {
+        out->steps = steps;
+        out->accepted = n_acc;
+        out->evaluations = n_eval;
+        out->applied = n_app;
+        out->J_best = J_best;
+    }
+    return MPS_OK;
+}
+
+mps_status mps_greedy_init(mps_model *m, int32_t max_pass, int32_t *passes, int64_t *placed,
+                           void *stream) {
+    if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    {
+        const mps_status vs = no_variant(m, "mps_greedy_init");
+        if (vs != MPS_OK) return vs;
+    }
+    if (max_pass < 1) return fail(MPS_E_INVALID_ARG, "max_pass must be >= 1 (got %d)", max_pass);
+    hipStream_t hs = (hipStream_t)stream;
+    if (capturing(hs)) return fail(MPS_E_NOT_CAPTURABLE, "mps_greedy_init during capture");
+    const DevModel &d = m->d;
+    if (d.N >= ((int64_t)1 << 31)) return fail(MPS_E_INVALID_ARG, "too many blocks");
+    const size_t lds = greedy_lds_bytes(d);
+    if (lds > (size_t)m->max_lds)
+        return fail(MPS_E_INVALID_ARG,
+                    "greedy initializer keeps T*S = %lld tonnages in LDS (%zu bytes); the device "
+                    "allows %d",
+                    (long long)d.T * d.S, lds, m->max_lds);
+    DeviceGuard g(m->device);
+    SearchBufs B;
+    char *ws = B.get<char>(greedy_ws_bytes(d));
+    int8_t *p = B.get<int8_t>(d.N);
+    int32_t *out = B.get<int32_t>(2);
+    if (!ws || !p || !out) return fail(MPS_E_OUT_OF_MEMORY, "greedy initializer buffers");
+    hipError_t e = launch_greedy(d, p, max_pass, ws, out, hs);
+    if (e == hipSuccess) e = launch_set_schedule(d, p, m->partial, m->chunks, hs);
+    int32_t h[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return dev_fail(e, "greedy initializer");
+    if (passes) *passes = h[0];
+    if (placed) *placed = h[1];
+    return MPS_OK;
+}
+
 mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_params *rp,
                       int32_t max_iter, mps_search_stats *out, void *stream) {
     if (!m) return fail(MPS_E_INVALID_ARG, "model is NULL");
+    {
+        const mps_status vs = no_variant(m, "mps_search");
+        if (vs != MPS_OK) return vs;
+    }
     if (mode != 0 && mode != 1) return fail(MPS_E_INVALID_ARG, "mode must be 0 or 1");
     if (k < 1 || k > MPS_MAX_TOPK)
         return fail(MPS_E_INVALID_ARG, "k must be in 1..%d (got %d)", MPS_MAX_TOPK, k);
@@ -889,6 +1251,10 @@ mps_status mps_batch_create(mps_model *const *models, const mps_batch_item *item
         const mps_model *m = models[i];
         const mps_batch_item &it = items[i];
         if (!m) return fail(MPS_E_INVALID_ARG, "model %d is NULL", i);
+        {
+            const mps_status vs = no_variant(m, "mps_batch_create");
+            if (vs != MPS_OK) return vs;
+        }
         if (m->device != models[0]->device)
             return fail(MPS_E_INVALID_ARG, "model %d is on another device", i);
         if (it.n < 0 || it.n >= ((int64_t)1 << 31))

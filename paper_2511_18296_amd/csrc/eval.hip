@@ -192,6 +192,7 @@ size_t eval_lds_bytes(const DevModel &m, const mps_moves &mv) {
 
 hipError_t launch_eval(const DevModel &m, const mps_moves &mv, float *score, uint8_t *flags,
                        float *dR, float *dPp, float *dPm, hipStream_t st) {
+    if (has_variant(m)) return launch_eval_var(m, mv, score, flags, dR, dPp, dPm, st);
     const bool comp = dR != nullptr;
     const unsigned tiles = (unsigned)((m.N + 63) / 64);
     const size_t base = tile_lds_layout(m, nullptr, nullptr);

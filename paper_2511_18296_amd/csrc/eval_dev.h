@@ -141,6 +141,20 @@ struct BlockShare {
 // issued unconditionally (invalid neighbours read b itself and are masked).
 __device__ __forceinline__ BlockInfo load_block(const DevModel &m, int64_t b) {
     BlockInfo bi;
+    if (m.csr) {   // explicit lists: the window from the lists (uniform branch)
+        bi.pb = gld(m.p + b);
+        bi.ton32 = gld(m.ton32 + b);
+        bi.ton64 = gld(m.ton64 + b);
+        bi.mb = gld(m.mb32 + b);
+        bi.Vb = gld(m.Vb32 + b);
+        bi.lo = 0;
+        bi.hi = m.T;
+        const int32_t j0 = gld(m.pred_ptr + b), j1 = gld(m.pred_ptr + b + 1);
+        for (int32_t j = j0; j < j1; ++j) bi.lo = max(bi.lo, (int32_t)gld(m.p + gld(m.pred_idx + j)));
+        const int32_t k0 = gld(m.succ_ptr + b), k1 = gld(m.succ_ptr + b + 1);
+        for (int32_t j = k0; j < k1; ++j) bi.hi = min(bi.hi, (int32_t)gld(m.p + gld(m.succ_idx + j)));
+        return bi;
+    }
     int32_t x, y, z;
     grid_coords(m, (int32_t)b, x, y, z);
     const int64_t nxy = (int64_t)m.nx * m.ny;

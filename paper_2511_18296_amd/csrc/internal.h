@@ -17,6 +17,7 @@ struct DevScalars {
     double mu, var, sigma;
     double R, Pp, Pm, J;
     double n_prec_viol;      // as double so the objective is one double[7]
+    double cvar_e;           // CVaR risk: CVaR_alpha(N) - mu (0 for the std measure)
     float sigma32, var32;
     int32_t n_bad_periods;   // schedule entries outside 0..T (clamped)
     int32_t pad;
@@ -79,6 +80,18 @@ struct DevModel {
     DevScalars *sc;
     const double *d64;     // [T+1] discount factors, d[T] = 0
     PeriodTables tab;
+    // precedence: csr = 0 the 1-5 stencil of the grid; csr = 1 the lists
+    // (predecessors of b: pred_idx[pred_ptr[b] .. pred_ptr[b+1]), successors
+    // likewise), at most MPS_MAX_DEGREE each
+    int32_t csr;
+    const int32_t *pred_ptr, *pred_idx, *succ_ptr, *succ_idx;
+    // objective variants: wmult [S][T+1] = d(t) sigma(s,t) (FP64; d(T) = 0),
+    // wmult32 the same in FP32; both NULL without a value multiplier.
+    // risk 0: mu - lambda sigma; risk 1: mu - lambda (mu - CVaR_alpha).
+    const double *wmult;
+    const float *wmult32;
+    int32_t risk;
+    double alpha;
     // list-mode per-block workspace
     float *blk_c;          // [N] (1/S) sum_s e_s v[s][b]
     float *blk_rem;        // [N] sum_s ore (removal clamp) for the current period
@@ -121,6 +134,37 @@ size_t rank_ws_bytes(const DevModel &m, int32_t k);
 hipError_t launch_rank(const DevModel &m, const float *grad, int32_t k, int32_t *blk,
                        int8_t *per, float *gain_out, int32_t *count, void *ws, hipStream_t st);
 hipError_t launch_integer_x(const DevModel &m, float *x, hipStream_t st);
+// Move evaluation under an objective variant (value multiplier and/or CVaR
+// risk); LDS bytes of its workgroup.
+constexpr int32_t kVariantMaxScen = 1024;
+size_t eval_var_lds_bytes(const DevModel &m);
+hipError_t launch_eval_var(const DevModel &m, const mps_moves &mv, float *score, uint8_t *flags,
+                           float *dR, float *dPp, float *dPm, hipStream_t st);
+__host__ __device__ inline bool has_variant(const DevModel &m) {
+    return m.wmult != nullptr || m.risk != 0;
+}
+// Cascading repair walk; mark is a device uint8 [N] workspace.  Re-derives
+// the state from the schedule afterwards (partial/chunks as for
+// launch_set_schedule).
+constexpr int32_t kCascadeMaxSet = 256;
+size_t cascade_lds_bytes(const DevModel &m);
+hipError_t launch_cascade(const DevModel &m, const mps_moves &mv, const int64_t *idx,
+                          const int32_t *count, int32_t max_cand, int32_t hard, int32_t max_set,
+                          int32_t *applied, uint8_t *mark, double *partial, int chunks,
+                          hipStream_t st);
+// LNS destroy step: region of the column tile [x0,x1) x [y0,y1) and its
+// descendants into reg (uint8 [N]), every region block set to never in the
+// model's schedule, and the repair move list (b, t < T) by increasing b into
+// lb/lt with its length in *count (device).
+hipError_t launch_lns_destroy(const DevModel &m, int32_t x0, int32_t x1, int32_t y0, int32_t y1,
+                              uint8_t *reg, int32_t *lb, int8_t *lt, int32_t *count,
+                              hipStream_t st);
+// Greedy initializer: writes the schedule into p (device int8 [N]) and
+// {passes, placed} into out (device int32 [2]).
+size_t greedy_ws_bytes(const DevModel &m);
+size_t greedy_lds_bytes(const DevModel &m);
+hipError_t launch_greedy(const DevModel &m, int8_t *p, int32_t max_pass, void *ws,
+                         int32_t *out, hipStream_t st);
 
 // Global-memory access through an explicitly global pointer.  Pointers held
 // in device-memory descriptors (not kernel arguments) are otherwise generic,
@@ -161,10 +205,60 @@ __device__ __forceinline__ void grid_coords(const DevModel &m, int32_t b,
     x = r - y * m.nx;
 }
 
+// Neighbour k of b: predecessor k (pred = true) or successor k, -1 when b
+// has fewer.  Stencil predecessors in the order up, x-1, x+1, y-1, y+1 (the
+// block on the bench above and its face neighbours); stencil successors by
+// increasing index; list neighbours in list order.  k < MPS_MAX_DEGREE.
+__device__ __forceinline__ int32_t nbr(const DevModel &m, int32_t b, int k, bool pred) {
+    if (m.csr) {
+        const int32_t *ptr = pred ? m.pred_ptr : m.succ_ptr;
+        const int32_t *ix = pred ? m.pred_idx : m.succ_idx;
+        const int32_t j = ptr[b] + k;
+        return j < ptr[b + 1] ? ix[j] : -1;
+    }
+    int32_t x, y, z;
+    grid_coords(m, b, x, y, z);
+    const int32_t nxy = m.nx * m.ny;
+    if (pred) {
+        if (z == 0) return -1;
+        const int32_t up = b - nxy;
+        switch (k) {
+            case 0: return up;
+            case 1: return x > 0 ? up - 1 : -1;
+            case 2: return x + 1 < m.nx ? up + 1 : -1;
+            case 3: return y > 0 ? up - m.nx : -1;
+            case 4: return y + 1 < m.ny ? up + m.nx : -1;
+            default: return -1;
+        }
+    }
+    if (z + 1 >= m.nz) return -1;
+    const int32_t dn = b + nxy;
+    switch (k) {
+        case 0: return y > 0 ? dn - m.nx : -1;
+        case 1: return x > 0 ? dn - 1 : -1;
+        case 2: return dn;
+        case 3: return x + 1 < m.nx ? dn + 1 : -1;
+        case 4: return y + 1 < m.ny ? dn + m.nx : -1;
+        default: return -1;
+    }
+}
+
 // max over predecessors of p (0 if none) and min over successors (T if none),
 // the two numbers that decide PREC_OK for every destination of b.
 __device__ __forceinline__ void prec_window(const DevModel &m, const int8_t *p,
                                             int32_t b, int32_t &lo, int32_t &hi) {
+    if (m.csr) {
+        const int32_t T = m.T;
+        lo = 0;
+        hi = T;
+        auto rd = [&](int32_t a) {
+            int32_t v = p[a];
+            return (v < 0 || v > T) ? T : v;
+        };
+        for (int32_t j = m.pred_ptr[b]; j < m.pred_ptr[b + 1]; ++j) lo = max(lo, rd(m.pred_idx[j]));
+        for (int32_t j = m.succ_ptr[b]; j < m.succ_ptr[b + 1]; ++j) hi = min(hi, rd(m.succ_idx[j]));
+        return;
+    }
     int32_t x, y, z;
     grid_coords(m, b, x, y, z);
     const int32_t nx = m.nx, nxy = m.nx * m.ny, T = m.T;

@@ -318,6 +318,10 @@ static RelaxWs relax_ws(void *ws, const DevModel &m, const FwdGeom &g) {
 __global__ void k_relax_init(DevModel m, uint16_t *nmask) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= m.N) return;
+    if (m.csr) {   // explicit lists: the precedence terms come from k_relax_prec_*_csr
+        nmask[b] = 0;
+        return;
+    }
     int32_t xx, yy, zz;
     grid_coords(m, (int32_t)b, xx, yy, zz);
     const uint32_t nb = (xx > 0 ? 2u : 0u) | (xx + 1 < m.nx ? 4u : 0u) | (yy > 0 ? 8u : 0u) |
@@ -1072,6 +1076,52 @@ static void go_fwd(const DevModel &m, const FwdGeom &g, const FwdArgs &a, hipStr
                            st, m, a);
 }
 
+// Precedence penalty under explicit lists, for the blocks of chunk g:
+// sum over b, a in Pred(b), t of max(0, x[b,t] - x[a,t])^2, added to the
+// chunk's precedence sum (the stencil part is 0 for such models).
+__global__ void __launch_bounds__(256) k_relax_prec_fwd_csr(DevModel m, const float *x,
+                                                            double *prq, int32_t G) {
+    __shared__ double red[4];
+    const int64_t per = (m.N + G - 1) / G;
+    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(m.N, b0 + per);
+    const int32_t T = m.T;
+    double acc = 0.0;
+    for (int64_t i = b0 * T + threadIdx.x; i < b1 * T; i += 256) {
+        const int64_t b = i / T;
+        const int32_t t = (int32_t)(i - b * T);
+        const float xb = x[i];
+        for (int32_t j = m.pred_ptr[b]; j < m.pred_ptr[b + 1]; ++j) {
+            const float e = xb - x[(int64_t)m.pred_idx[j] * T + t];
+            if (e > 0.0f) acc += (double)e * (double)e;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) prq[blockIdx.x] += ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Its derivative, added to grad (scaled by dJ): -2 mu_prec (sum over
+// predecessors a of max(0, x[b,t] - x[a,t]) - sum over successors c of
+// max(0, x[c,t] - x[b,t])).
+__global__ void __launch_bounds__(256) k_relax_prec_bwd_csr(DevModel m, const float *x,
+                                                            const double *dJ, double mu_prec,
+                                                            float *grad) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int32_t T = m.T;
+    if (i >= m.N * T) return;
+    const int64_t b = i / T;
+    const int32_t t = (int32_t)(i - b * T);
+    const float xb = x[i];
+    float pp = 0.0f, ps = 0.0f;
+    for (int32_t j = m.pred_ptr[b]; j < m.pred_ptr[b + 1]; ++j)
+        pp += fmaxf(xb - x[(int64_t)m.pred_idx[j] * T + t], 0.0f);
+    for (int32_t j = m.succ_ptr[b]; j < m.succ_ptr[b + 1]; ++j)
+        ps += fmaxf(x[(int64_t)m.succ_idx[j] * T + t] - xb, 0.0f);
+    const float scale = dJ ? (float)dJ[0] : 1.0f;
+    grad[i] -= scale * (float)(2.0 * mu_prec) * (pp - ps);
+}
+
 hipError_t launch_relaxed_fwd(const DevModel &m, const float *x, const mps_relax_params &rp,
                               double *J_out, void *saved, void *ws, hipStream_t st) {
     const RelaxK rk{m.lambda, rp.mu_proc, rp.mu_mine, rp.mu_prec, m.pcap, m.mcap};
@@ -1086,6 +1136,9 @@ hipError_t launch_relaxed_fwd(const DevModel &m, const float *x, const mps_relax
         case 4: go_fwd<2, 4>(m, g, fa, st); break;
         default: go_fwd<1, 8>(m, g, fa, st); break;
     }
+    if (m.csr)
+        hipLaunchKernelGGL(k_relax_prec_fwd_csr, dim3((unsigned)g.G), dim3(256), 0, st, m, x,
+                           r.prq, g.G);
     const RedArgs ra{r.P, g.Cp, g.ncols, g.G, g.nred, pad_scen(m.S), r.pq, r.pmq, r.prq,
                      make_div((uint32_t)m.T)};
     hipLaunchKernelGGL(k_relax_fwd_reduce, dim3((unsigned)g.nred), dim3(256), 0, st, m, ra, rk,
@@ -1117,6 +1170,9 @@ hipError_t launch_relaxed_bwd(const DevModel &m, const float *x, const mps_relax
     else
         g.MT == 2 ? go_bwd<1, 2>(m, g, a, rk, sv, st)
                   : (g.MT == 4 ? go_bwd<1, 4>(m, g, a, rk, sv, st) : go_bwd<1, 8>(m, g, a, rk, sv, st));
+    if (m.csr)
+        hipLaunchKernelGGL(k_relax_prec_bwd_csr, dim3((unsigned)((m.N * m.T + 255) / 256)),
+                           dim3(256), 0, st, m, x, dJ, rp.mu_prec, grad);
     return hipGetLastError();
 }
 

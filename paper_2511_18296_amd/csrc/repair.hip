@@ -48,7 +48,8 @@ namespace mps {
 
 constexpr int kWaves = 8;   // candidates scored per round
 constexpr int kThreads = 64 * kWaves;
-constexpr int kNbr = 11;   // the block, 5 predecessors, 5 successors
+constexpr int kDeg = MPS_MAX_DEGREE;
+constexpr int kNbr = 1 + 2 * kDeg;   // the block, its predecessors, its successors
 constexpr size_t kBatchBytes = 40960;   // candidate records per LDS batch buffer
 constexpr int kPf = (int)(kBatchBytes / (16 * kThreads));   // float4 per thread per batch
 static_assert((kWaves == 4 || kWaves == 8) && kPf >= 1,
@@ -146,7 +147,7 @@ constexpr double kNever = -1e300;
 // ore words.
 struct CandHdr {
     int32_t b, t;           // b < 0: invalid entry
-    uint32_t nb[kNbr];      // index 0 the block itself, 1..5 predecessors, 6..10 successors
+    uint32_t nb[kNbr];      // index 0 the block itself, 1..kDeg predecessors, then successors
     int32_t pad;
     double mb, Vb, ton;
 };
@@ -222,20 +223,11 @@ __device__ __forceinline__ bool decode(const DevModel &m, const mps_moves &mv, i
     return b >= 0 && (int64_t)b < m.N && t >= 0 && t <= m.T;
 }
 
-// Neighbour k of block b: 0 = b, 1..5 predecessors, 6..10 successors; -1
-// outside the grid.
+// Neighbour k of block b: 0 = b, 1..kDeg predecessors, kDeg+1..2 kDeg
+// successors; -1 where b has fewer.
 __device__ __forceinline__ int32_t neighbour(const DevModel &m, int32_t b, int k) {
     if (k == 0) return b;
-    int32_t x, y, z;
-    grid_coords(m, b, x, y, z);
-    const int j = (k - 1) % 5;
-    const int dz = k <= 5 ? -1 : 1;
-    const int dx = j == 1 ? -1 : j == 2 ? 1 : 0;
-    const int dy = j == 3 ? -1 : j == 4 ? 1 : 0;
-    if (z + dz < 0 || z + dz >= m.nz || x + dx < 0 || x + dx >= m.nx || y + dy < 0 ||
-        y + dy >= m.ny)
-        return -1;
-    return b + dz * m.nx * m.ny + dy * m.nx + dx;
+    return k <= kDeg ? nbr(m, b, k - 1, true) : nbr(m, b, k - 1 - kDeg, false);
 }
 
 __device__ __forceinline__ int32_t cand_count(const int32_t *count, int32_t max_cand) {
@@ -563,8 +555,8 @@ __global__ void __launch_bounds__(kThreads) k_repair_walk(DevModel m, int32_t n_
                     const uint32_t own = __builtin_amdgcn_readlane(cur, 0);
                     const int32_t pk = (int32_t)(cur & 0xffu);
                     const bool bad_prec =
-                        __ballot((C.nb & kNbPresent) && ((lane >= 1 && lane <= 5 && pk > t) ||
-                                                         (lane >= 6 && lane <= 10 && t > pk))) !=
+                        __ballot((C.nb & kNbPresent) && ((lane >= 1 && lane <= kDeg && pk > t) ||
+                                                         (lane > kDeg && lane < kNbr && t > pk))) !=
                         0ull;
                     if (!(own & kMoved) && !bad_prec && t != p0) {
                         const double ton = C.ton, tmc = ton - pcap;

@@ -64,7 +64,9 @@ __global__ void __launch_bounds__(64) k_state_partial(DevModel m, const int8_t *
     const int32_t T = m.T;
     double *dl = acc + (size_t)T * 64;
     for (int t = 0; t < T; ++t) acc[t * 64 + tid] = 0.0;
-    for (int t = tid; t <= T; t += 64) dl[t] = m.d64[t];
+    // scenario rows discount with d(t) sigma(s,t) under a value multiplier
+    const double *drow = (m.wmult && r < m.S) ? m.wmult + (size_t)r * (T + 1) : m.d64;
+    for (int t = tid; t <= T; t += 64) dl[t] = drow[t];
     __syncthreads();
     const int64_t per = (m.N + chunks - 1) / chunks;
     const int64_t b0 = (int64_t)ch * per, b1 = min(m.N, b0 + per);
@@ -103,6 +105,13 @@ __global__ void __launch_bounds__(64) k_state_partial(DevModel m, const int8_t *
             const int32_t t = m.p[b];
             if (t < T) acc[t * 64 + tid] += m.ton64[b];
             // predecessor pairs with p[a] > p[b]
+            if (m.csr) {
+                double nv = bad ? 1.0 : 0.0;
+                for (int32_t j = m.pred_ptr[b]; j < m.pred_ptr[b + 1]; ++j)
+                    if (m.p[m.pred_idx[j]] > t) nv += 1.0;
+                nacc += nv;
+                continue;
+            }
             int32_t x, y, z;
             grid_coords(m, (int32_t)b, x, y, z);
             const int64_t a = b - nxy;
@@ -222,6 +231,26 @@ __global__ void __launch_bounds__(256) k_prep(DevModel m) {
         for (int64_t i = tid; i < (int64_t)S * T; i += 256) pp += hinge64(m.O[i], m.pcap);
         pp = block_sum_f64(pp, red);
         for (int32_t i = tid; i < S; i += 256) m.e32[i] = (float)(m.Ns[i] - mu);
+        // CVaR of the lower alpha tail: scenario i of rank r (value, then
+        // index) weighs 1 below rank k-1, alpha*S - k + 1 at rank k-1
+        double cv = 0.0;
+        const double aS = m.alpha * S;
+        int32_t kq = (int32_t)ceil(aS);
+        kq = kq < 1 ? 1 : (kq > S ? S : kq);
+        if (m.risk == 1) {
+            double part = 0.0;
+            for (int32_t i = tid; i < S; i += 256) {
+                const double x = m.Ns[i];
+                int32_t r = 0;
+                for (int32_t j = 0; j < S; ++j) {
+                    const double y = m.Ns[j];
+                    r += (y < x || (y == x && j < i)) ? 1 : 0;
+                }
+                if (r < kq - 1) part += x;
+                else if (r == kq - 1) part += (aS - (kq - 1)) * x;
+            }
+            cv = block_sum_f64(part, red) / aS;
+        }
         if (tid == 0) {
             double pm = 0.0;
             for (int32_t u = 0; u < T; ++u) pm += hinge64(m.M[u], m.mcap);
@@ -232,7 +261,8 @@ __global__ void __launch_bounds__(256) k_prep(DevModel m) {
             sc->sigma = sigma;
             sc->sigma32 = (float)sigma;
             sc->var32 = (float)var;
-            sc->R = mu - m.lambda * sigma;
+            sc->cvar_e = m.risk == 1 ? cv - mu : 0.0;
+            sc->R = m.risk == 1 ? mu - m.lambda * (mu - cv) : mu - m.lambda * sigma;
             sc->Pp = m.pen_proc * pp / S;
             sc->Pm = m.pen_mine * pm;
             sc->J = sc->R - sc->Pp - sc->Pm;

@@ -39,14 +39,14 @@ def test_version_and_error_text():
 
 def _params(**kw):
     from paper_2511_18296_amd import binding
-    d = dict(nx=4, ny=4, nz=2, n_scen=8, n_periods=3, reserved=0, discount_rate=0.08,
+    d = dict(nx=4, ny=4, nz=2, n_scen=8, n_periods=3, precedence=0, discount_rate=0.08,
              lam=0.5, pen_proc=100.0, pen_mine=100.0, proc_cap=1e6, mine_cap=1e6)
     d.update(kw)
     return binding.Params(**d)
 
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(n_scen=0), dict(n_scen=5000),
-                                 dict(n_periods=0), dict(n_periods=127), dict(reserved=1),
+                                 dict(n_periods=0), dict(n_periods=127), dict(precedence=2),
                                  dict(discount_rate=-1.0), dict(lam=float("nan")),
                                  dict(pen_proc=-1.0), dict(mine_cap=float("inf"))])
 def test_build_rejects_bad_params_before_any_device_work(bad):
@@ -54,7 +54,7 @@ def test_build_rejects_bad_params_before_any_device_work(bad):
     h = C.c_void_p()
     prm = _params(**bad)
     st = binding.lib.mps_build_model(C.byref(prm), C.c_void_p(1), C.c_void_p(2),
-                                     C.c_void_p(3), None, C.byref(h))
+                                     C.c_void_p(3), None, None, None, C.byref(h))
     assert st == 1, binding.lib.mps_last_error()
     assert h.value is None
     assert binding.lib.mps_last_error()
@@ -65,12 +65,70 @@ def test_null_arguments_rejected():
     L = binding.lib
     h = C.c_void_p()
     prm = _params()
-    assert L.mps_build_model(C.byref(prm), None, None, None, None, C.byref(h)) == 1
-    assert L.mps_build_model(C.byref(prm), None, None, None, None, None) == 1
+    assert L.mps_build_model(C.byref(prm), None, None, None, None, None, None, C.byref(h)) == 1
+    assert L.mps_build_model(C.byref(prm), None, None, None, None, None, None, None) == 1
     assert L.mps_destroy_model(None) == 1
     assert L.mps_set_schedule(None, None, None) == 1
     assert L.mps_eval_moves(None, None, None, None, None, None, None, None) == 1
     assert L.mps_repair(None, None, None, None, 0, 0, None, None) == 1
+
+
+def _lists(N, edges):
+    """CSR predecessor lists from (block, predecessor) pairs."""
+    import numpy as np
+    ptr = np.zeros(N + 1, dtype=np.int32)
+    idx = []
+    for b in range(N):
+        lst = [a for (c, a) in edges if c == b]
+        idx += lst
+        ptr[b + 1] = len(idx)
+    return ptr, np.asarray(idx if idx else [0], dtype=np.int32)
+
+
+@pytest.mark.parametrize("case", ["self", "range", "repeat", "indegree", "outdegree",
+                                  "no_lists", "lists_without_csr"])
+def test_build_rejects_bad_predecessor_lists(case):
+    """Explicit predecessor lists (Eq. 15's sets) are validated on the host
+    before any device work."""
+    from paper_2511_18296_amd import binding
+    N = 32
+    csr = 1
+    if case == "self":
+        ptr, idx = _lists(N, [(5, 5)])
+    elif case == "range":
+        ptr, idx = _lists(N, [(5, 32)])
+    elif case == "repeat":
+        ptr, idx = _lists(N, [(5, 1), (5, 1)])
+    elif case == "indegree":
+        ptr, idx = _lists(N, [(20, a) for a in range(10)])
+    elif case == "outdegree":
+        ptr, idx = _lists(N, [(c, 0) for c in range(1, 11)])
+    elif case == "no_lists":
+        ptr = idx = None
+    else:
+        ptr, idx = _lists(N, [(5, 1)])
+        csr = 0
+    prm = _params(precedence=csr)
+    h = C.c_void_p()
+    lp = [None if a is None else a.ctypes.data_as(C.c_void_p) for a in (ptr, idx)]
+    st = binding.lib.mps_build_model(C.byref(prm), C.c_void_p(1), C.c_void_p(2),
+                                     C.c_void_p(3), lp[0], lp[1], None, C.byref(h))
+    assert st == 1, binding.lib.mps_last_error()
+    assert h.value is None
+
+
+def test_valid_predecessor_lists_pass_the_host_checks():
+    from paper_2511_18296_amd import binding
+    N = 32
+    ptr, idx = _lists(N, [(c, c - 16) for c in range(16, 32)] + [(17, 0), (17, 2)])
+    prm = _params(precedence=1)
+    h = C.c_void_p()
+    st = binding.lib.mps_build_model(C.byref(prm), C.c_void_p(1), C.c_void_p(2),
+                                     C.c_void_p(3), ptr.ctypes.data_as(C.c_void_p),
+                                     idx.ctypes.data_as(C.c_void_p), None, C.byref(h))
+    # past the list checks the call needs a GPU (MPS_E_DEVICE here) or
+    # device pointers (MPS_E_INVALID_ARG for these fake ones)
+    assert st in (1, 3) and b"predecessor" not in binding.lib.mps_last_error()
 
 
 @pytest.mark.parametrize("n,k,ws", [(10, 0, 1 << 20), (10, 8193, 1 << 20), (-1, 4, 1 << 20),
