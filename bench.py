@@ -77,30 +77,50 @@ def eval_bytes(N, S, T, D):
     return 4 * S * N + 4 * W * N + 8 * N + 4 * N + N + 5 * N * D
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(inst, k, min_seconds=10.0, max_reps=200):
     """The FP64 oracle on the host: full steps of the same workload (all moves,
     top-k, repair from the seeded schedule), repeated until at least
-    min_seconds of host time have passed."""
+    min_seconds of host time have passed, with every OpenMP thread of the
+    process and then with one thread."""
     import numpy as np
     import oracle
     o = oracle.Oracle(inst)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     D = inst.T + 1
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        sc, fl = o.eval_moves(inst.p0, include_never=True, threads=threads)
-        idx, _ = oracle.topk(sc, fl, k)
-        o.repair(inst.p0, (idx // D).astype(np.int32), (idx % D).astype(np.int8))
-        reps += 1
-        dt = time.perf_counter() - t0
-        if dt >= min_seconds or reps >= max_reps:
-            break
     n = inst.N * D
+
+    def run(nt, secs):
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            sc, fl = o.eval_moves(inst.p0, include_never=True, threads=nt)
+            idx, _ = oracle.topk(sc, fl, k)
+            o.repair(inst.p0, (idx // D).astype(np.int32), (idx % D).astype(np.int8))
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= secs or reps >= max_reps:
+                return reps, dt
+
+    reps, dt = run(threads, min_seconds)
+    reps1, dt1 = run(1, min_seconds)
     return {"value": reps * n * inst.S / dt, "unit": "move-scenario evals/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{reps} full steps (each: eval of all {n:,} moves x {inst.S} scenarios, "
-                      f"top-{k}, repair) of the same instance, {dt:.1f} s"}
+                      f"top-{k}, repair) of the same instance, {dt:.1f} s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"value": reps1 * n * inst.S / dt1, "cores": 1,
+                              "sample": f"{reps1} full steps, {dt1:.1f} s"}}
 
 
 def batch_bytes(insts, moves):
@@ -237,6 +257,73 @@ def kernel_legs(models, inst):
     return out
 
 
+def rows_leg(model, seed_state, inst, k):
+    """The rows beyond the plain engine on the 54,000-block instance: the
+    greedy initializer, cascading repair over the best moves without the
+    precedence requirement, evaluation of all moves under the value
+    multiplier and under CVaR10; and the LNS + SA driver on the paper-scale
+    instance (32,000 blocks, S = 50, T = 15)."""
+    import numpy as np
+    import torch
+    import mpsgen
+    from paper_2511_18296_amd.binding import Model, MoveSet, TopK, NOOP, BAD
+    out = {}
+    D = inst.T + 1
+    M = inst.N * D
+    # greedy initializer (synchronising call: host wall time)
+    model.restore_state(seed_state)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    passes, placed = model.greedy_init()
+    out["greedy_init"] = {"ms": (time.perf_counter() - t0) * 1e3, "passes": passes,
+                          "placed": placed, "J": model.objective()["J"]}
+    # cascading repair: candidates without the precedence requirement
+    model.restore_state(seed_state)
+    ex = MoveSet(True, True)
+    sc, fl = model.eval_moves(ex)
+    tk = TopK(M, k)
+    idx, _, cnt = tk(sc, fl, require=0, forbid=NOOP | BAD)
+    applied = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def casc(i):
+        model.restore_state(seed_state)
+        model.repair_cascade(ex, idx, cnt, max_set=64, applied=applied)
+
+    t_c = burst_seconds(casc, 3)
+    out["cascade_repair"] = {"us": t_c * 1e6, "candidates": k,
+                             "applied": int(applied.item()), "max_set": 64}
+    # objective variants: all 1,134,000 moves
+    model.restore_state(seed_state)
+    mult = np.random.default_rng(7).uniform(0.6, 1.4, size=(inst.S, inst.T))
+    score = torch.empty(M, dtype=torch.float32, device="cuda")
+    flags = torch.empty(M, dtype=torch.uint8, device="cuda")
+    for name, mu, risk in (("multiplier", mult, 0), ("cvar10", None, 1),
+                           ("multiplier_cvar10", mult, 1)):
+        model.set_objective_variant(mu, risk, 0.1)
+        t = burst_seconds(lambda i: model.eval_moves(ex, out=[score, flags]), 5)
+        out[f"eval_{name}"] = {"us": t * 1e6, "move_scenario_evals_per_s": M * inst.S / t}
+    model.set_objective_variant(None, 0)
+    model.restore_state(seed_state)
+    # LNS + SA on the paper-scale instance
+    pinst = mpsgen.paper_scale()
+    pm = Model.from_instance(pinst)
+    n_iter, tile = 1, 10
+    K = ((pinst.nx + tile - 1) // tile) * ((pinst.ny + tile - 1) // tile)
+    u = np.random.default_rng(4).random(n_iter * K)
+    J0 = pm.objective()["J"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, traj = pm.lns_sa(n_iter, tile, 1024, 8, 1e7, 1e6, 0.9, u)
+    dt = time.perf_counter() - t0
+    out["lns_sa_paper_scale"] = {"seconds": dt, "steps": st["steps"],
+                                 "accepted": st["accepted"],
+                                 "moves_evaluated": st["evaluations"],
+                                 "moves_per_s": st["evaluations"] / dt,
+                                 "applied": st["applied"], "J_start": J0,
+                                 "J_best": st["J_best"], "tile": tile, "k": 1024, "rounds": 8}
+    return out
+
+
 def search_leg(model, seed_state, k):
     """Gradient-ranked search vs exhaustive search from the same seeded schedule."""
     import torch
@@ -252,6 +339,17 @@ def search_leg(model, seed_state, k):
                      "applied": int(st["applied"]), "seconds": dt}
     JE, JG = out["exhaustive"]["J"], out["gradient_ranked"]["J"]
     out["rel_diff"] = abs(JG - JE) / abs(JE)
+    # Both loops stop at a schedule that an exhaustive round cannot improve,
+    # i.e. at a local optimum of the same neighbourhood; which one depends on
+    # the order of the applied moves.  The exhaustive loop alone, run with a
+    # different list length, shows how far apart such end points lie.
+    spread = {}
+    for kk in (k // 2, 2 * k):
+        model.restore_state(seed_state)
+        st = model.search(0, kk, RELAX, max_iter=10000)
+        spread[str(kk)] = {"J": st["J"], "rel_diff_to_exhaustive": abs(st["J"] - JE) / abs(JE),
+                           "iterations": int(st["iterations"])}
+    out["exhaustive_other_k"] = spread
     out["relax_weights"] = list(RELAX)
     return out
 
@@ -260,6 +358,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--no-rows", action="store_true", help="skip the next-row legs")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--copies", type=int, default=8)
     ap.add_argument("--k", type=int, default=4096)
@@ -327,17 +426,63 @@ def main():
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps); timing {args.steps} steps")
+    log(f"warmup done ({args.warmup} steps); {args.steps} eager steps with phase events")
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(args.warmup + i, ev[i])
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall_eager = time.perf_counter() - t0
+    # every copy's eager result (a step restores its copy's seed, so one
+    # more step of each copy gives it, also for copies the timed steps missed)
+    for r in range(args.copies):
+        step(r)
+    torch.cuda.synchronize()
+    eager_J = [m.objective()["J"] for m in models]
 
     t_rest = sum(e[4].elapsed_time(e[0]) for e in ev) / args.steps * 1e-3
     t_eval = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps * 1e-3
     t_topk = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps * 1e-3
     t_rep = sum(e[2].elapsed_time(e[3]) for e in ev) / args.steps * 1e-3
+
+    # The timed steps: each step captured once per instance copy as a HIP
+    # graph (restore, evaluation, top-k, repair) and replayed; every replay
+    # must end at the eager result.
+    graphs = []
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        for r in range(args.copies):
+            step(r)   # warm the capture stream
+    torch.cuda.current_stream().wait_stream(cap)
+    torch.cuda.synchronize()
+    for r in range(args.copies):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cap):
+            step(r)
+        graphs.append(g)
+    for r in range(args.copies):
+        graphs[r].replay()
+    torch.cuda.synchronize()
+    for r, m in enumerate(models):
+        assert m.objective()["J"] == eager_J[r], "graph replay differs from the eager step"
+    log(f"timing {args.steps} graph-replayed steps")
+    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        gev[i][0].record()
+        graphs[i % args.copies].replay()
+        gev[i][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for r, m in enumerate(models):
+        assert m.objective()["J"] == eager_J[r], "graph replay differs from the eager step"
+    per_step = sorted(a.elapsed_time(b) * 1e-3 for a, b in gev)
+
+    def pct(xs, q):
+        return xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))]
+
     ms = wall / args.steps * 1e3
     value = M * S * args.steps / wall
     B = eval_bytes(N, S, T, D)
@@ -391,8 +536,17 @@ def main():
                      "timing": f"{burst} back-to-back launches between two HIP events",
                      "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
                      "source_sha1": eval_source_sha()},
+        "timing": {"value": f"{args.steps} graph-replayed steps between two host "
+                            "synchronisations (wall clock)",
+                   "step_us_median": pct(per_step, 0.5) * 1e6,
+                   "step_us_p10": pct(per_step, 0.1) * 1e6,
+                   "step_us_p90": pct(per_step, 0.9) * 1e6,
+                   "per_step_events": f"event pair around each of the {args.steps} replays",
+                   "eager_ms_per_step": wall_eager / args.steps * 1e3},
         "phases_us": {"restore": t_rest * 1e6, "eval": t_eval * 1e6, "topk": t_topk * 1e6,
-                      "repair": t_rep * 1e6},
+                      "repair": t_rep * 1e6,
+                      "method": "eager steps, events between the phases (each includes "
+                                "its event markers)"},
         "eval_move_scenario_evals_per_s": M * S / t_eval_kernel,
         "repair": {"applied_per_step": n_applied[0],
                    "us_per_applied_move": t_rep * 1e6 / max(1, n_applied[0]),
@@ -400,6 +554,10 @@ def main():
         "legs": legs,
         "final_J": [o["J"] for o in objs],
     }
+    if not args.no_rows:
+        log("rows: greedy, cascade, variants, LNS ...")
+        out["rows"] = rows_leg(models[0], seeds[0], inst, args.k)
+        log(f"rows: {json.dumps(out['rows'])}")
     if not args.no_search:
         log("search comparison (exhaustive vs gradient-ranked) ...")
         out["search"] = search_leg(models[0], seeds[0], args.k)

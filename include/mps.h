@@ -205,7 +205,10 @@ size_t mps_topk_ws_bytes(int64_t n, int32_t k);
  * ascending; write the first min(k, #kept) to idx (int64 [k]) and top_score
  * (float [k], may be NULL), and that count to *count (device int32).
  * Entries past the count are set to -1 / -inf.  1 <= k <= MPS_MAX_TOPK,
- * 0 <= n < 2^31.  ws: device workspace of mps_topk_ws_bytes(n, k) bytes. */
+ * 0 <= n < 2^31.  ws: device workspace of mps_topk_ws_bytes(n, k) bytes,
+ * zero-filled by the caller before its first use; every call leaves it ready
+ * for the next (a workspace is reusable for any n and k it is large enough
+ * for).  Calls that share a workspace must not overlap. */
 mps_status mps_topk(const float *score, const uint8_t *flags, int64_t n,
                     int32_t k, uint8_t require, uint8_t forbid, int64_t *idx,
                     float *top_score, int32_t *count, void *ws,
@@ -214,7 +217,7 @@ mps_status mps_topk(const float *score, const uint8_t *flags, int64_t n,
 /* mps_topk for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same selection and outputs, with the workspace in a device array the
- * library owns (about 33 MiB per device, held until the process ends)
+ * library owns (33 MiB per device, held until the process ends)
  * instead of a caller buffer.  Limits: 0 <= n <= 2^21 (2,097,152 items),
  * 1 <= k <= MPS_MAX_TOPK; beyond them MPS_E_INVALID_ARG before any work.
  * Runs on the current device; allocates nothing.  Every call on one device
@@ -303,7 +306,9 @@ size_t mps_rank_ws_bytes(const mps_model *m, int32_t k);
  * (the first-order change of J along x(p') - x(p)); returns the k best
  * (gain descending, move index b*(T+1)+t' ascending) as block (int32 [k]),
  * period (int8 [k]), gain (float [k], may be NULL) and *count (device int32);
- * entries past the count are -1.  1 <= k <= MPS_MAX_TOPK. */
+ * entries past the count are -1.  1 <= k <= MPS_MAX_TOPK.  ws: device
+ * workspace of mps_rank_ws_bytes(m, k) bytes, zero-filled by the caller
+ * before its first use (every call leaves it ready for the next). */
 mps_status mps_rank_moves(mps_model *m, const float *grad_x, int32_t k, int32_t *block,
                           int8_t *period, float *gain, int32_t *count, void *ws,
                           size_t ws_bytes, void *stream);

@@ -366,7 +366,11 @@ class Model:
     def rank_moves(self, grad, k, stream=None):
         _dev(grad, torch.float32, (self.N, self.T), "grad")
         nb = int(lib.mps_rank_ws_bytes(self.h, int(k)))
-        ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        # zero-filled once; each call leaves it ready for the next
+        cache = self.__dict__.setdefault("_rank_ws", {})
+        ws = cache.get(nb)
+        if ws is None:
+            ws = cache[nb] = torch.zeros(nb, dtype=torch.uint8, device=self.device)
         blk = torch.empty(k, dtype=torch.int32, device=self.device)
         per = torch.empty(k, dtype=torch.int8, device=self.device)
         gain = torch.empty(k, dtype=torch.float32, device=self.device)
@@ -449,7 +453,8 @@ class TopK:
     def __init__(self, n, k, device="cuda"):
         self.n, self.k = int(n), int(k)
         self.ws_bytes = int(lib.mps_topk_ws_bytes(self.n, self.k))
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        # zero-filled before the first call; every call leaves it so
+        self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=device)
         self.idx = torch.empty(self.k, dtype=torch.int64, device=device)
         self.score = torch.empty(self.k, dtype=torch.float32, device=device)
         self.count = torch.zeros(1, dtype=torch.int32, device=device)

@@ -82,6 +82,16 @@ struct SearchBufs {
         ptrs.push_back(p);
         return (T *)p;
     }
+    // A workspace whose first `zero` bytes start zero (top-k and ranking
+    // workspaces); nullptr if the allocation or the clearing fails.
+    char *get_zeroed(size_t bytes, size_t zero, hipStream_t st) {
+        char *p = get<char>(bytes);
+        if (p && hipMemsetAsync(p, 0, zero < bytes ? zero : bytes, st) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
 };
 
 }  // namespace
@@ -305,7 +315,8 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
         delete m;                            \
         return st;                           \
     }
-    ALLOC(v_, (size_t)S * N);
+    const int64_t vld = (N + 31) / 32 * 32;   // 128-byte rows
+    ALLOC(v_, (size_t)S * vld);
     ALLOC(ore_, (size_t)W * N);
     ALLOC(ton64, N);
     ALLOC(ton32, N);
@@ -354,6 +365,8 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     ALLOC(blk_c, N);
     ALLOC(blk_rem, N);
     ALLOC(blk_info, N);
+    uint32_t *tmark = nullptr;
+    ALLOC(tmark, (size_t)(N + 63) / 64);
     ALLOC(m->partial, (size_t)m->chunks * (S + 1) * (T + 1));
     ALLOC(m->obj_dev, 8);
     {
@@ -392,6 +405,7 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     }
 #undef ALLOC
     d.v = v_;
+    d.vld = vld;
     d.ore = ore_;
     d.ton64 = ton64;
     d.ton32 = ton32;
@@ -417,6 +431,7 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     d.blk_c = blk_c;
     d.blk_rem = blk_rem;
     d.blk_info = blk_info;
+    d.tmark = tmark;
 
     // discount factors: d(0) = 1, d(t) = d(t-1)/(1+rate), d(T) = 0
     std::vector<double> dh((size_t)T + 1);
@@ -432,7 +447,10 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
         delete m;
         return dev_fail(err, what);
     };
-    if ((st = chk(hipMemcpyAsync(v_, v, sizeof(float) * S * N, hipMemcpyDeviceToDevice, hs),
+    if ((st = chk(hipMemsetAsync(v_, 0, sizeof(float) * S * vld, hs), "padding of v")) != MPS_OK)
+        return st;
+    if ((st = chk(hipMemcpy2DAsync(v_, sizeof(float) * vld, v, sizeof(float) * N,
+                                   sizeof(float) * N, S, hipMemcpyDeviceToDevice, hs),
                   "copy of v")) != MPS_OK)
         return st;
     if ((st = chk(hipMemcpyAsync(ore_, ore_bits, sizeof(uint32_t) * W * N,
@@ -447,6 +465,9 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
         return st;
     if ((st = chk(hipMemsetD32Async((hipDeviceptr_t)m->rep_first, INT32_MAX, (size_t)N, hs),
                   "repair marks")) != MPS_OK)
+        return st;
+    if ((st = chk(hipMemsetAsync(tmark, 0, sizeof(uint32_t) * ((N + 63) / 64), hs),
+                  "tile marks")) != MPS_OK)
         return st;
     if ((st = chk(hipMemcpyAsync(d64, dh.data(), sizeof(double) * (T + 1),
                                  hipMemcpyHostToDevice, hs),
@@ -852,7 +873,7 @@ mps_status mps_lns_sa(mps_model *m, const mps_lns_params *prm, const double *u, 
     int8_t *lt = B.get<int8_t>(nm);
     float *score = B.get<float>(nm);
     uint8_t *flags = B.get<uint8_t>(nm);
-    char *tws = B.get<char>(topk_ws_bytes(nm, P.k));
+    char *tws = B.get_zeroed(topk_ws_bytes(nm, P.k), topk_ws_zero_bytes(), hs);
     int64_t *idx = B.get<int64_t>(P.k);
     int32_t *cnt = B.get<int32_t>(4);   // [0] list length, [1] top-k count, [2] applied
     double *objd = B.get<double>(8);
@@ -1015,7 +1036,7 @@ mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_par
     SearchBufs B;
     float *score = B.get<float>(nm);
     uint8_t *flags = B.get<uint8_t>(nm);
-    char *tws = B.get<char>(topk_ws_bytes(nm, k));
+    char *tws = B.get_zeroed(topk_ws_bytes(nm, k), topk_ws_zero_bytes(), hs);
     int64_t *idx = B.get<int64_t>(k);
     int32_t *cnt = B.get<int32_t>(4);
     float *x = nullptr, *grad = nullptr, *gain = nullptr, *lscore = nullptr;
@@ -1027,16 +1048,18 @@ mps_status mps_search(mps_model *m, int32_t mode, int32_t k, const mps_relax_par
         x = B.get<float>((size_t)d.N * d.T);
         grad = B.get<float>((size_t)d.N * d.T);
         saved = B.get<char>(relaxed_saved_bytes(d));
-        rws = B.get<char>(rank_ws_bytes(d, k));
+        rws = B.get_zeroed(rank_ws_bytes(d, k), rank_ws_bytes(d, k), hs);
         rblk = B.get<int32_t>(k);
         rper = B.get<int8_t>(k);
         gain = B.get<float>(k);
         lscore = B.get<float>(k);
         lflags = B.get<uint8_t>(k);
-        ltws = B.get<char>(topk_ws_bytes(k, k));
+        ltws = B.get_zeroed(topk_ws_bytes(k, k), topk_ws_zero_bytes(), hs);
     }
-    for (void *p : B.ptrs)
-        if (!p) return fail(MPS_E_OUT_OF_MEMORY, "mps_search buffers");
+    if (!score || !flags || !tws || !idx || !cnt ||
+        (mode == 1 && (!x || !grad || !saved || !rws || !rblk || !rper || !gain || !lscore ||
+                       !lflags || !ltws)))
+        return fail(MPS_E_OUT_OF_MEMORY, "mps_search buffers");
     mps_moves ex{1, 1, 0, nullptr, nullptr};
     mps_moves lst{0, 1, k, rblk, rper};
     int64_t iters = 0, evals = 0, applied_total = 0;

@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(kCT) k_cascade_walk(DevModel m, mps_moves mv, 
         for (int32_t s = tid; s < S; s += kCT) {
             double acc = Ns[s];
             for (int32_t q = 0; q < n; ++q)
-                acc += (double)m.v[(int64_t)s * m.N + sh.set[q]] * (dl[t] - dl[sh.setp[q]]);
+                acc += (double)m.v[(int64_t)s * m.vld + sh.set[q]] * (dl[t] - dl[sh.setp[q]]);
             Np[s] = acc;
             s1 += acc;
         }

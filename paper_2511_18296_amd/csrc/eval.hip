@@ -56,7 +56,8 @@ __global__ void __launch_bounds__(kNT, KCH <= 25 ? 8 : 1) k_eval_exh(DevModel m,
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t b0 = (int64_t)blockIdx.x * 64;
+    // each XCD streams one contiguous range of tiles
+    const int64_t b0 = xcd_tile(blockIdx.x, gridDim.x) * 64;
     const int64_t b = b0 + lane;
     const bool valid = b < m.N;
 
@@ -132,7 +133,20 @@ __global__ void __launch_bounds__(kNT, KCH <= 25 ? 8 : 1) k_eval_exh(DevModel m,
 }
 
 // ---- list mode: per-block quantities, then one thread per move --------------
-__global__ void __launch_bounds__(kNT) k_block_prep(DevModel m) {
+// A short list touches few of the 64-block tiles: it marks them first, and the
+// block pass skips every unmarked tile (clearing each mark it consumes, so the
+// marks are zero again between calls).  A long list touches nearly every tile
+// (a tile escapes n uniform moves with probability about exp(-n/tiles)), and
+// the pass covers all of them without marks.
+__global__ void k_mark_tiles(int64_t n, int64_t N, const int32_t *blk, uint32_t *mark) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = blk[i];
+    if (b >= 0 && b < N) mark[b >> 6] = 1u;
+}
+
+__global__ void __launch_bounds__(kNT) k_block_prep(DevModel m, uint32_t *mark) {
+    if (mark != nullptr && mark[blockIdx.x] == 0u) return;   // uniform over the workgroup
     extern __shared__ __align__(16) char lds[];
     TileLds L;
     tile_lds_layout(m, lds, &L);
@@ -151,7 +165,8 @@ __global__ void __launch_bounds__(kNT) k_block_prep(DevModel m) {
         L.ore[w * 64 + lane] = valid ? m.ore[(int64_t)w * m.N + b] : 0u;
     const TabView tv = commit_tables(m, L, tp);
     L.cpart[wave * 64 + lane] = wave_dot(m, m.e32, b, valid, s0, s1, x);
-    __syncthreads();
+    __syncthreads();   // every thread has read the mark
+    if (mark != nullptr && tid == 0) mark[blockIdx.x] = 0u;
     const float c = tile_c(L, lane, m.S);
     if (wave == 0 && valid) {
         auto ow = [&](int32_t w) { return L.ore[w * 64 + lane]; };
@@ -215,8 +230,15 @@ hipError_t launch_eval(const DevModel &m, const mps_moves &mv, float *score, uin
             go(k_eval_exh<false, kCH>);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_block_prep, dim3(tiles), dim3(kNT), base, st, m);
-    if (mv.n > 0) {
+    if (mv.n == 0) return hipGetLastError();
+    uint32_t *mark = nullptr;
+    if (mv.n < 8 * (int64_t)tiles) {
+        mark = m.tmark;
+        hipLaunchKernelGGL(k_mark_tiles, dim3((unsigned)((mv.n + 255) / 256)), dim3(256), 0, st,
+                           mv.n, m.N, mv.block, mark);
+    }
+    hipLaunchKernelGGL(k_block_prep, dim3(tiles), dim3(kNT), base, st, m, mark);
+    {
         const unsigned g = (unsigned)((mv.n + kNT - 1) / kNT);
         if (comp)
             hipLaunchKernelGGL(k_eval_list<true>, dim3(g), dim3(kNT), base, st, m, mv.n,

@@ -317,7 +317,7 @@ __device__ __forceinline__ void issue_rows(const DevModel &m, int64_t b, bool va
                                            int32_t s1, float (&x)[KCH]) {
     const float *vp = m.v + (valid ? b : 0);
 #pragma unroll
-    for (int k = 0; k < KCH; ++k) x[k] = gld_nt(vp + (int64_t)min(s + k, m.S - 1) * m.N);
+    for (int k = 0; k < KCH; ++k) x[k] = gld_nt(vp + (int64_t)min(s + k, m.S - 1) * m.vld);
 }
 
 // e: the scenario weights in global memory, padded by 64 entries past S, so
@@ -353,7 +353,7 @@ __device__ __forceinline__ float wave_dot(const DevModel &m, const float *e, int
             float y[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                y[k] = s + k < s1 ? gld_nt(vp + (int64_t)(s + k) * m.N) : 0.0f;
+                y[k] = s + k < s1 ? gld_nt(vp + (int64_t)(s + k) * m.vld) : 0.0f;
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 if (s + k < s1) acc = fmaf(gld(e + s + k), y[k], acc);

@@ -233,7 +233,7 @@ __device__ __forceinline__ void var_column(const DevModel &m, int32_t b, int32_t
         if (q >= NQ) continue;
         const int32_t s = lane + 64 * q;
         if (s >= m.S) continue;
-        v[q] = m.v[(int64_t)s * m.N + b];
+        v[q] = m.v[(int64_t)s * m.vld + b];
         ob[q] = (m.ore[(int64_t)(s >> 5) * m.N + b] >> (s & 31)) & 1u;
     }
 }

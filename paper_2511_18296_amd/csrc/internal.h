@@ -64,7 +64,8 @@ struct DevModel {
     int32_t S, T, W, nx, ny, nz;
     double lambda, pen_proc, pen_mine, pcap, mcap;
     double ton_min, ton_max;
-    const float *v;        // [S][N]
+    const float *v;        // [S][vld]: row s holds v[s][0 .. N), zero-padded
+    int64_t vld;           // row stride of v: N rounded up to 32 (128-byte rows)
     const uint32_t *ore;   // [W][N]
     const double *ton64;   // [N]
     const float *ton32;    // [N]
@@ -96,6 +97,7 @@ struct DevModel {
     float *blk_c;          // [N] (1/S) sum_s e_s v[s][b]
     float *blk_rem;        // [N] sum_s ore (removal clamp) for the current period
     int32_t *blk_info;     // [N] p | maxPred << 8 | minSucc << 16
+    uint32_t *tmark;       // [ceil(N/64)] tiles a move list touches; zero between calls
 };
 
 // Sets the thread-local text mps_last_error() returns; returns st.
@@ -116,6 +118,9 @@ hipError_t launch_eval(const DevModel &m, const mps_moves &mv, float *score,
                        uint8_t *flags, float *dR, float *dPp, float *dPm,
                        hipStream_t st);
 size_t topk_ws_bytes(int64_t n, int32_t k);
+// Leading bytes of a top-k workspace that must be zero when a call starts
+// (every call leaves them zero).
+size_t topk_ws_zero_bytes();
 hipError_t launch_topk(const float *score, const uint8_t *flags, int64_t n,
                        int32_t k, uint8_t req, uint8_t forbid, int64_t *idx,
                        float *top_score, int32_t *count, void *ws,
@@ -284,6 +289,19 @@ __device__ __forceinline__ void prec_window(const DevModel &m, const int8_t *p,
         if (y > 0) hi = min(hi, rd(c - nx));
         if (y + 1 < m.ny) hi = min(hi, rd(c + nx));
     }
+}
+
+// Workgroups of a launch are dealt to the eight XCDs round-robin (workgroup
+// i to XCD i % 8), each XCD with its own L2.  xcd_tile maps workgroup i to a
+// tile so that every XCD takes one contiguous range of tiles (a bijection on
+// 0 .. n-1 for a grid of n workgroups).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t n) {
+    const int64_t x = i % kXcds, j = i / kXcds;
+    const int64_t q = n / kXcds, r = n % kXcds;
+    // XCDs below r hold q + 1 workgroups, the others q
+    const int64_t start = x * q + (x < r ? x : r);
+    return start + j;
 }
 
 __device__ __forceinline__ double hinge64(double x, double cap) {

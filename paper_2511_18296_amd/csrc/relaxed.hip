@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(kRT, 2) k_relax_fwd_chunk(DevModel m, FwdArgs 
         for (int r = 0; r < kRBs; ++r) {
             const int32_t i = min(i0 + r, max(nrow - 1, 0));
             const int32_t s = min(s_lo + wave + kSW * i, S - 1);
-            const float *row = m.v + (int64_t)s * N + bc;
+            const float *row = m.v + (int64_t)s * m.vld + bc;
 #pragma unroll
             for (int q = 0; q < Q; ++q)
                 buf[r][q] = ld_off(row, min(ln + 64u * q, (uint32_t)(nb - 1)));
@@ -857,7 +857,7 @@ __global__ void __launch_bounds__(kRT, MT <= 2 ? 4 : 2) k_relax_bwd_tile(DevMode
         for (int r = 0; r < kRB; ++r) {
             const int32_t i = min(i0 + r, max(nrow - 1, 0));
             const int32_t s = min(wave + 8 * i, S - 1);
-            const float *row = m.v + (int64_t)s * N + b0;
+            const float *row = m.v + (int64_t)s * m.vld + b0;
 #pragma unroll
             for (int q = 0; q < Q; ++q) buf[r][q] = ld_off(row, (uint32_t)min(lane + 64 * q, nb - 1));
         }

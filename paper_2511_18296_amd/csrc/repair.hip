@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(64) k_repair_gather(DevModel m, mps_moves mv, 
         h->nb[lane] = w;
     }
     for (int32_t s = lane; s < Sp; s += 64)
-        v[s] = (b >= 0 && s < S) ? m.v[(int64_t)s * m.N + b] : 0.0f;
+        v[s] = (b >= 0 && s < S) ? m.v[(int64_t)s * m.vld + b] : 0.0f;
     // ore bits of scenarios >= S cleared
     for (int32_t w = lane; w < W; w += 64) {
         const int32_t left = S - 32 * w;

@@ -15,11 +15,11 @@ __global__ void k_block_stats(DevModel m, float *mb32, float *Vb32, double *mb64
     int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= m.N) return;
     double s1 = 0.0;
-    for (int32_t s = 0; s < m.S; ++s) s1 += (double)m.v[(int64_t)s * m.N + b];
+    for (int32_t s = 0; s < m.S; ++s) s1 += (double)m.v[(int64_t)s * m.vld + b];
     double mu = s1 / m.S;
     double s2 = 0.0;
     for (int32_t s = 0; s < m.S; ++s) {
-        double e = (double)m.v[(int64_t)s * m.N + b] - mu;
+        double e = (double)m.v[(int64_t)s * m.vld + b] - mu;
         s2 += e * e;
     }
     double var = s2 / m.S;
@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(64) k_state_partial(DevModel m, const int8_t *
     double nacc = 0.0;
     if (r < m.S) {
         const int32_t s = r;
-        const float *vrow = m.v + (int64_t)s * m.N;
+        const float *vrow = m.v + (int64_t)s * m.vld;
         const uint32_t *orow = m.ore + (int64_t)(s >> 5) * m.N;
         const uint32_t bit = 1u << (s & 31);
         for (int64_t bb = b0 + tid; bb < b1; bb += 64 * kStU) {
