@@ -56,8 +56,7 @@ __global__ void __launch_bounds__(kNT, KCH <= 25 ? 8 : 1) k_eval_exh(DevModel m,
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    // each XCD streams one contiguous range of tiles
-    const int64_t b0 = xcd_tile(blockIdx.x, gridDim.x) * 64;
+    const int64_t b0 = (int64_t)blockIdx.x * 64;
     const int64_t b = b0 + lane;
     const bool valid = b < m.N;
 

@@ -291,19 +291,6 @@ __device__ __forceinline__ void prec_window(const DevModel &m, const int8_t *p,
     }
 }
 
-// Workgroups of a launch are dealt to the eight XCDs round-robin (workgroup
-// i to XCD i % 8), each XCD with its own L2.  xcd_tile maps workgroup i to a
-// tile so that every XCD takes one contiguous range of tiles (a bijection on
-// 0 .. n-1 for a grid of n workgroups).
-constexpr int kXcds = 8;
-__device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t n) {
-    const int64_t x = i % kXcds, j = i / kXcds;
-    const int64_t q = n / kXcds, r = n % kXcds;
-    // XCDs below r hold q + 1 workgroups, the others q
-    const int64_t start = x * q + (x < r ? x : r);
-    return start + j;
-}
-
 __device__ __forceinline__ double hinge64(double x, double cap) {
     return x > cap ? x - cap : 0.0;
 }

@@ -115,21 +115,11 @@ __global__ void __launch_bounds__(256) k_hist0(const float *score, const uint8_t
         q[u] = i < n && item_key(score, flags, i, req, forbid, key[u]);
     }
     __syncthreads();
-    // scores crowd into few digits: one LDS atomic per distinct digit of a
-    // wave (lanes grouped by ballot) instead of one per lane
-    const int lane = threadIdx.x & 63;
+    // one LDS atomic per item (grouping the lanes of a digit by ballot first
+    // measured slower: the scores of a wave spread over many digits)
 #pragma unroll
-    for (int u = 0; u < kItems; ++u) {
-        const int d = q[u] ? digit_of(key[u], 0) : -1;
-        uint64_t pending = __ballot(d >= 0);
-        while (pending) {
-            const int leader = __ffsll((unsigned long long)pending) - 1;
-            const int dl = __shfl(d, leader);
-            const uint64_t same = __ballot(d == dl);
-            if (lane == leader) atomicAdd(&lh[dl], (uint32_t)__popcll(same));
-            pending &= ~same;
-        }
-    }
+    for (int u = 0; u < kItems; ++u)
+        if (q[u]) atomicAdd(&lh[digit_of(key[u], 0)], 1u);
     __syncthreads();
     uint32_t *rep = w.z->hist[blockIdx.x % kRep];
     for (int i = threadIdx.x; i < kBins; i += 256) {
@@ -266,6 +256,7 @@ __global__ void __launch_bounds__(256) k_compact0(const float *score, const uint
 // keys still needed, refine them by the next digit; then every remaining
 // candidate is needed, and the chosen keys plus the remaining candidates are
 // exactly the top min(k, total) (keys are unique).
+constexpr int kRU = 8;   // candidates per thread in flight in the refinement
 __global__ void __launch_bounds__(kRefineThreads) k_refine(TopkWs w) {
     __shared__ uint32_t lh[kBins];
     __shared__ uint32_t part[256];
@@ -288,8 +279,19 @@ __global__ void __launch_bounds__(kRefineThreads) k_refine(TopkWs w) {
         for (int i = tid; i < nb; i += kRefineThreads) lh[i] = 0;
         if (tid == 0) n_dst_s = 0;
         __syncthreads();
-        for (int32_t i = tid; i < ns; i += kRefineThreads)
-            atomicAdd(&lh[digit_of(src[i], level)], 1u);
+        // candidates in chunks of kRU per thread, every load of a chunk in
+        // flight before the first use
+        for (int32_t c0 = 0; c0 < ns; c0 += kRU * kRefineThreads) {
+            uint64_t key[kRU];
+#pragma unroll
+            for (int u = 0; u < kRU; ++u) {
+                const int32_t i = c0 + tid + u * kRefineThreads;
+                key[u] = i < ns ? src[i] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < kRU; ++u)
+                if (c0 + tid + u * kRefineThreads < ns) atomicAdd(&lh[digit_of(key[u], level)], 1u);
+        }
         __syncthreads();
         const int32_t k_rem = k_rem_s;
         select_digit(lh, nb, k_rem, part, res);
@@ -298,15 +300,22 @@ __global__ void __launch_bounds__(kRefineThreads) k_refine(TopkWs w) {
         const bool last = level == kLevels - 1;
         // digit above -> out; equal -> dst (keys are unique, so at the last
         // level the equal digit is taken as well)
-        const int32_t n_up = ((ns + 63) / 64) * 64;
-        for (int32_t i = tid; i < n_up; i += kRefineThreads) {
-            const bool in = i < ns;
-            const uint64_t key = in ? src[i] : 0ull;
-            const int d = in ? digit_of(key, level) : -1;
-            const bool to_out = in && (take_all || d > sel || (last && d == sel));
-            const bool to_dst = in && !take_all && !last && d == sel;
-            wave_append(to_out, key, w.out, &n_out_s);
-            wave_append(to_dst, key, dst, &n_dst_s);
+        for (int32_t c0 = 0; c0 < ns; c0 += kRU * kRefineThreads) {
+            uint64_t key[kRU];
+#pragma unroll
+            for (int u = 0; u < kRU; ++u) {
+                const int32_t i = c0 + tid + u * kRefineThreads;
+                key[u] = i < ns ? src[i] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < kRU; ++u) {
+                const bool in = c0 + tid + u * kRefineThreads < ns;
+                const int d = in ? digit_of(key[u], level) : -1;
+                const bool to_out = in && (take_all || d > sel || (last && d == sel));
+                const bool to_dst = in && !take_all && !last && d == sel;
+                wave_append(to_out, key[u], w.out, &n_out_s);
+                wave_append(to_dst, key[u], dst, &n_dst_s);
+            }
         }
         __threadfence_block();
         __syncthreads();
@@ -323,7 +332,19 @@ __global__ void __launch_bounds__(kRefineThreads) k_refine(TopkWs w) {
     __syncthreads();
     // every remaining candidate is chosen: append them after the others
     const int32_t no = n_out_s, ns = n_src_s;
-    for (int32_t i = tid; i < ns; i += kRefineThreads) w.out[no + i] = src[i];
+    for (int32_t c0 = 0; c0 < ns; c0 += kRU * kRefineThreads) {
+        uint64_t key[kRU];
+#pragma unroll
+        for (int u = 0; u < kRU; ++u) {
+            const int32_t i = c0 + tid + u * kRefineThreads;
+            key[u] = i < ns ? src[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kRU; ++u) {
+            const int32_t i = c0 + tid + u * kRefineThreads;
+            if (i < ns) w.out[no + i] = key[u];
+        }
+    }
     if (tid == 0) w.ctrl->n_final = no + ns;
     // the level-0 histogram and counters are no longer read in this call:
     // leave them zero for the next one
@@ -346,7 +367,28 @@ __global__ void __launch_bounds__(256) k_rank(TopkWs w, int32_t k, int64_t *idx,
     const int32_t tot = w.ctrl->n_final;
     const int32_t tot32 = (tot + 31) & ~31;
     const int tid = threadIdx.x;
-    for (int32_t j = tid; j < tot32; j += 256) keys[j] = j < tot ? w.out[j] : 0ull;
+    {
+        // every load in flight before the first store: key pairs tid + 256 u
+        // (out[] is allocated in whole 256-byte units, so pairs up to tot32
+        // stay inside it; entries from tot on are replaced by 0)
+        constexpr int kPairs = (MPS_MAX_TOPK + 511) / 512;
+        ulonglong2 buf[kPairs];
+#pragma unroll
+        for (int u = 0; u < kPairs; ++u) {
+            const int32_t j = 2 * (tid + 256 * u);
+            buf[u] = j < tot32 ? *(const ulonglong2 *)(w.out + j) : make_ulonglong2(0ull, 0ull);
+        }
+#pragma unroll
+        for (int u = 0; u < kPairs; ++u) {
+            const int32_t j = 2 * (tid + 256 * u);
+            if (j < tot32) {
+                ulonglong2 v = buf[u];
+                if (j >= tot) v.x = 0ull;
+                if (j + 1 >= tot) v.y = 0ull;
+                *(ulonglong2 *)(keys + j) = v;
+            }
+        }
+    }
     __syncthreads();
     const int kj = tid & (kRankKeys - 1), q = tid >> 4;
     const int32_t i = blockIdx.x * kRankKeys + kj;
