@@ -440,7 +440,13 @@ typedef struct mps_batch mps_batch;
 
 /* Build a batch over n_models models (all on one device; they must outlive
  * the batch) and their move lists.  Allocates the descriptor table, the work
- * queue and the counters; the tuning of each model comes from the process
+ * queue, the counters and, per model, the order in which its moves are
+ * scored (4 bytes per move: within each move item, the positions sorted by
+ * moved block, so that neighbouring lanes read neighbouring blocks' data).
+ * Every move is scored once and its results stay at its own position, so a
+ * move list that changes after this call still gives exact results; only the
+ * locality is lost until mps_batch_set_tuning recomputes the order.  The
+ * tuning of each model comes from the process
  * tuning cache (filled by mps_batch_autotune) or from defaults.  Two batches
  * that share a model must not run at the same time (they share its block
  * workspace), nor may a batch run concurrently with mps_eval_moves in list

@@ -1139,6 +1139,11 @@ mps_tuning default_tuning(int32_t S) {
     return t;
 }
 
+// Moves sorted by block together: the whole move items that first reach this
+// many moves (so an item takes a contiguous sub-range of its range's blocks,
+// and the scores and flags a range's items write stay within about 80 KB).
+constexpr int32_t kSortRange = 16384;
+
 bool tuning_ok(const mps_tuning &t) {
     return t.reserved == 0 && t.tiles_per_item >= 1 && t.tiles_per_item <= 64 &&
            t.moves_per_item >= 512 && t.moves_per_item <= 65536 && t.moves_per_item % 512 == 0 &&
@@ -1155,6 +1160,8 @@ struct mps_batch {
     std::vector<mps_batch_item> items;
     std::vector<mps_tuning> tune;
     std::vector<int32_t> order;   // models by decreasing block-value bytes
+    std::vector<int32_t *> perm;  // per model: block order of its moves (batch_sort_moves)
+    std::vector<int32_t> perm_mpi;   // the range length each perm was sorted with
     BatchInst *d_insts = nullptr;
     int2 *d_items1 = nullptr, *d_items2 = nullptr;
     int32_t *d_order = nullptr;
@@ -1210,6 +1217,7 @@ struct mps_batch {
             I.m = models[i]->d;
             I.blk = it.block;
             I.per = it.period;
+            I.perm = perm[i];
             I.n = it.n;
             I.score = it.score;
             I.flags = it.flags;
@@ -1222,6 +1230,20 @@ struct mps_batch {
             I.moves_per_item = tune[i].moves_per_item;
             I.n2 = (int32_t)((it.n + I.moves_per_item - 1) / I.moves_per_item);
             I.rows = tune[i].rows;
+        }
+        {
+            DeviceGuard g(device);
+            for (int32_t i = 0; i < n; ++i) {
+                // sorted ranges of several move items: each item then takes a
+                // contiguous sub-range of the blocks of its range
+                const int32_t mpi = hi[i].moves_per_item;
+                const int32_t seg = mpi * std::max(1, (kSortRange + mpi - 1) / mpi);
+                if (items[i].n <= 0 || perm_mpi[i] == seg) continue;
+                const hipError_t e =
+                    batch_sort_moves(items[i].block, items[i].n, seg, perm[i], nullptr);
+                if (e != hipSuccess) return dev_fail(e, "block order of a batch's moves");
+                perm_mpi[i] = seg;
+            }
         }
         std::vector<int2> q1, q2;
         for (int32_t i : order)
@@ -1253,6 +1275,7 @@ struct mps_batch {
         hipFree(d_items2);
         hipFree(d_order);
         hipFree(d_ctl);
+        for (int32_t *p : perm) hipFree(p);
     }
 };
 
@@ -1332,6 +1355,11 @@ mps_status mps_batch_create(mps_model *const *models, const mps_batch_item *item
     if (e == hipSuccess)
         e = hipMalloc((void **)&b->d_ctl, sizeof(uint32_t) * (size_t)batch_ctl_words(n_models));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    b->perm.assign(n_models, nullptr);
+    b->perm_mpi.assign(n_models, 0);
+    for (int32_t i = 0; i < n_models && e == hipSuccess; ++i)
+        if (items[i].n > 0)
+            e = hipMalloc((void **)&b->perm[i], sizeof(int32_t) * (size_t)items[i].n);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         delete b;
@@ -1363,10 +1391,13 @@ mps_status mps_batch_set_tuning(mps_batch *b, int32_t i, const mps_tuning *t) {
         return fail(MPS_E_INVALID_ARG,
                     "tuning out of range (tiles_per_item 1..64, moves_per_item a multiple of "
                     "512 in 512..65536, rows 8/16/32, reserved 0)");
-    if (i < 0)
+    if (i < 0) {
         std::fill(b->tune.begin(), b->tune.end(), *t);
-    else
+        std::fill(b->perm_mpi.begin(), b->perm_mpi.end(), 0);   // order recomputed
+    } else {
         b->tune[i] = *t;
+        b->perm_mpi[i] = 0;
+    }
     return b->rebuild();
 }
 
@@ -1459,9 +1490,9 @@ mps_status mps_batch_autotune(mps_batch *b, int32_t reps, double *best_us, void 
         for (int param = 0; param < 3; ++param) {
             static const int kRows[] = {8, 16, 32};
             static const int kTiles[] = {1, 2, 4, 8};
-            static const int kMoves[] = {1024, 2048, 4096, 8192, 16384};
+            static const int kMoves[] = {1024, 2048, 4096, 8192, 16384, 32768};
             const int *vals = param == 0 ? kRows : param == 1 ? kTiles : kMoves;
-            const int nv = param == 0 ? 3 : param == 1 ? 4 : 5;
+            const int nv = param == 0 ? 3 : param == 1 ? 4 : 6;
             for (int v = 0; v < nv; ++v) {
                 std::vector<mps_tuning> saved = b->tune;
                 bool changed = false;

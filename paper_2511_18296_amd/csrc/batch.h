@@ -61,6 +61,10 @@ struct BatchInst {
     DevModel m;
     const int32_t *blk;
     const int8_t *per;
+    // positions 0 .. n-1 ordered by moved block (stable) within ranges of
+    // whole move items: a move item scores the moves of its stretch of this
+    // order, so that neighbouring lanes read neighbouring blocks' data
+    const int32_t *perm;
     int64_t n;
     float *score;
     uint8_t *flags;
@@ -92,5 +96,11 @@ struct BatchLaunch {
 size_t batch_lds_bytes(const DevModel &m);
 hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st);
 hipError_t batch_occupancy(size_t lds_bytes, int *per_cu);
+
+// perm[0 .. n) = the positions of blk[0 .. n) ordered by block, stably,
+// within each range [j*len, (j+1)*len).  Allocates its temporary buffers;
+// synchronises the stream.
+hipError_t batch_sort_moves(const int32_t *blk, int64_t n, int32_t len, int32_t *perm,
+                            hipStream_t st);
 
 }  // namespace mps

@@ -135,12 +135,14 @@ __device__ void batch_moves(const DevModel &m, const BatchInst &I, char *lds, in
     const TablePrefetch tp = issue_tables(m);
     for (int j = tid; j < kSegBins; j += kBT) h[j] = 0u;
     const TabView tv = commit_tables(m, L, tp);   // barrier inside
+    // moves in block order (perm), results and keys at their own positions
     for (int64_t i = i0 + tid; i < i1; i += kBT) {
-        const MoveOut o = list_move(m, tv, L, gld(I.blk + i), (int32_t)gld(I.per + i));
-        gst(I.score + i, o.score);
-        gst(I.flags + i, o.flags);
+        const int64_t p = gld(I.perm + i);
+        const MoveOut o = list_move(m, tv, L, gld(I.blk + p), (int32_t)gld(I.per + p));
+        gst(I.score + p, o.score);
+        gst(I.flags + p, o.flags);
         uint64_t key;
-        if (key_from(o.score, o.flags, i, req, forbid, key))
+        if (key_from(o.score, o.flags, p, req, forbid, key))
             atomicAdd(&h[(int)(key >> 52)], 1u);
     }
     __syncthreads();
