@@ -1139,11 +1139,6 @@ mps_tuning default_tuning(int32_t S) {
     return t;
 }
 
-// Moves sorted by block together: the whole move items that first reach this
-// many moves (so an item takes a contiguous sub-range of its range's blocks,
-// and the scores and flags a range's items write stay within about 80 KB).
-constexpr int32_t kSortRange = 16384;
-
 bool tuning_ok(const mps_tuning &t) {
     return t.reserved == 0 && t.tiles_per_item >= 1 && t.tiles_per_item <= 64 &&
            t.moves_per_item >= 512 && t.moves_per_item <= 65536 && t.moves_per_item % 512 == 0 &&
@@ -1234,10 +1229,11 @@ struct mps_batch {
         {
             DeviceGuard g(device);
             for (int32_t i = 0; i < n; ++i) {
-                // sorted ranges of several move items: each item then takes a
-                // contiguous sub-range of the blocks of its range
-                const int32_t mpi = hi[i].moves_per_item;
-                const int32_t seg = mpi * std::max(1, (kSortRange + mpi - 1) / mpi);
+                // one sorted range per move item (longer ranges, which give
+                // each item a contiguous stretch of blocks, measured slower:
+                // the items of a range then write the same lines of scores
+                // from different XCDs)
+                const int32_t seg = hi[i].moves_per_item;
                 if (items[i].n <= 0 || perm_mpi[i] == seg) continue;
                 const hipError_t e =
                     batch_sort_moves(items[i].block, items[i].n, seg, perm[i], nullptr);

@@ -61,9 +61,9 @@ struct BatchInst {
     DevModel m;
     const int32_t *blk;
     const int8_t *per;
-    // positions 0 .. n-1 ordered by moved block (stable) within ranges of
-    // whole move items: a move item scores the moves of its stretch of this
-    // order, so that neighbouring lanes read neighbouring blocks' data
+    // positions 0 .. n-1 ordered by moved block (stable) within each range
+    // of moves_per_item: a move item scores its moves in this order, so that
+    // neighbouring lanes read neighbouring blocks' data
     const int32_t *perm;
     int64_t n;
     float *score;

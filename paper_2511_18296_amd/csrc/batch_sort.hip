@@ -1,6 +1,6 @@
 // batch_sort.hip -- the block order of a batch's move lists, computed once
-// when the batch is built or retuned: within each range of a few move items,
-// the positions sorted by moved block (a stable segmented radix sort, so
+// when the batch is built or retuned: within each move item's range of
+// moves, the positions sorted by moved block (a stable segmented radix sort, so
 // equal blocks keep their list order).  The move items then score their
 // moves in that order, and neighbouring lanes read neighbouring blocks' data.
 #include <hipcub/hipcub.hpp>
