@@ -301,11 +301,11 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     d.ton_min = tmin;
     d.ton_max = tmax;
 
-    float *v_, *ton32, *mb32, *Vb32, *e32, *blk_c, *blk_rem;
+    float *v_, *ton32, *mb32, *Vb32, *e32;
     uint32_t *ore_, *full_add, *full_rem;
     double *ton64, *mb64, *Vb64, *Ns, *O, *M, *d64;
     int8_t *p;
-    int32_t *tcnt, *trng, *blk_info;
+    int32_t *tcnt, *trng;
     AddEntry *ladd, *padd;
     RemEntry *lrem, *prem;
     DevScalars *sc;
@@ -362,9 +362,8 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
         padd = (AddEntry *)(arena + o_pa);
         prem = (RemEntry *)(arena + o_pr);
     }
-    ALLOC(blk_c, N);
-    ALLOC(blk_rem, N);
-    ALLOC(blk_info, N);
+    ListRec *blk_rec = nullptr;
+    ALLOC(blk_rec, N);
     uint32_t *tmark = nullptr;
     ALLOC(tmark, (size_t)(N + 63) / 64);
     ALLOC(m->partial, (size_t)m->chunks * (S + 1) * (T + 1));
@@ -428,9 +427,7 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     d.tab.rng = trng;
     d.tab.add_packed = padd;
     d.tab.rem_packed = prem;
-    d.blk_c = blk_c;
-    d.blk_rem = blk_rem;
-    d.blk_info = blk_info;
+    d.blk_rec = blk_rec;
     d.tmark = tmark;
 
     // discount factors: d(0) = 1, d(t) = d(t-1)/(1+rate), d(T) = 0

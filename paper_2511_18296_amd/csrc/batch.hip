@@ -117,9 +117,7 @@ __device__ void batch_blocks(const DevModel &m, char *lds, int32_t t0, int32_t t
         const float c = tile_c(L, lane, m.S);
         if (wave == 0 && valid) {
             auto ow = [&](int32_t w) { return L.ore[w * 64 + lane]; };
-            gst(m.blk_c + b, c);
-            gst(m.blk_rem + b, removal_term(m, tv, bi.pb, bi.ton32, ow));
-            gst(m.blk_info + b, (int32_t)(bi.pb | (bi.lo << 8) | (bi.hi << 16)));
+            put_list_rec(m, b, c, removal_term(m, tv, bi.pb, bi.ton32, ow), bi, ow);
         }
         __syncthreads();   // cpart and ore are rewritten by the next tile
     }

@@ -169,9 +169,7 @@ __global__ void __launch_bounds__(kNT) k_block_prep(DevModel m, uint32_t *mark) 
     const float c = tile_c(L, lane, m.S);
     if (wave == 0 && valid) {
         auto ow = [&](int32_t w) { return L.ore[w * 64 + lane]; };
-        m.blk_c[b] = c;
-        m.blk_rem[b] = removal_term(m, tv, bi.pb, bi.ton32, ow);
-        m.blk_info[b] = bi.pb | (bi.lo << 8) | (bi.hi << 16);
+        put_list_rec(m, b, c, removal_term(m, tv, bi.pb, bi.ton32, ow), bi, ow);
     }
 }
 

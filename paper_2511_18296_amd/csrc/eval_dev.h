@@ -491,8 +491,29 @@ __device__ __forceinline__ void score_block_post(int wave, int lane, const Block
     }
 }
 
-// One listed move (b, t) from the per-block quantities the list pass wrote
-// (blk_c, blk_rem, blk_info); a move out of range is BAD with score -FLT_MAX.
+// Writes block b's record (one lane per block; four 16-byte stores).
+template <class OreWord>
+__device__ __forceinline__ void put_list_rec(const DevModel &m, int64_t b, float c, float rem,
+                                             const BlockInfo &bi, OreWord ore_word) {
+    ListRec r;
+    r.c = c;
+    r.rem = rem;
+    r.info = bi.pb | (bi.lo << 8) | (bi.hi << 16);
+    r.ton32 = bi.ton32;
+    r.mb = bi.mb;
+    r.Vb = bi.Vb;
+    r.ton64 = bi.ton64;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) r.ore[w] = w < m.W ? ore_word(w) : 0u;
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const u4 *src = (const u4 *)&r;
+    u4 *dst = (u4 *)(m.blk_rec + b);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gst(dst + k, src[k]);
+}
+
+// One listed move (b, t) from the record the list pass wrote; a move out of
+// range is BAD with score -FLT_MAX.
 __device__ __forceinline__ MoveOut list_move(const DevModel &m, const TabView &tv,
                                              const TileLds &L, int32_t b, int32_t t) {
     if (b < 0 || (int64_t)b >= m.N || t < 0 || t > m.T) {
@@ -502,13 +523,27 @@ __device__ __forceinline__ MoveOut list_move(const DevModel &m, const TabView &t
         o.dr = o.dpp = o.dpm = 0.0f;
         return o;
     }
-    const int32_t info = gld(m.blk_info + b);
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const u4 *rp = (const u4 *)(m.blk_rec + b);
+    const u4 q0 = gld(rp), q1 = gld(rp + 1);
+    u4 q2 = {0u, 0u, 0u, 0u}, q3 = q2;
+    if (m.W <= 8) {   // uniform
+        q2 = gld(rp + 2);
+        q3 = gld(rp + 3);
+    }
+    const float c = __uint_as_float(q0.x), rem = __uint_as_float(q0.y);
+    const int32_t info = (int32_t)q0.z;
+    const float ton32 = __uint_as_float(q0.w), mb = __uint_as_float(q1.x),
+                Vb = __uint_as_float(q1.y);
+    const double ton64 = __hiloint2double((int)q1.w, (int)q1.z);
     const int32_t pb = info & 0xff, lo = (info >> 8) & 0xff, hi = (info >> 16) & 0xff;
-    auto ow = [&](int32_t w) { return gld(m.ore + (int64_t)w * m.N + b); };
-    return score_move(m, tv, L.d64, L.Ms, t, pb, lo, hi, gld(m.blk_c + b), gld(m.blk_rem + b),
-                      gld(m.ton32 + b), gld(m.ton64 + b), gld(m.mb32 + b), gld(m.Vb32 + b),
-                      gld(&m.sc->var32), gld(&m.sc->sigma32),
-                      (float)m.lambda, (float)(m.pen_proc / m.S), ow);
+    const uint32_t ow8[8] = {q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+    auto ow = [&](int32_t w) {
+        return m.W <= 8 ? ow8[w & 7] : gld(m.ore + (int64_t)w * m.N + b);
+    };
+    return score_move(m, tv, L.d64, L.Ms, t, pb, lo, hi, c, rem, ton32, ton64, mb, Vb,
+                      gld(&m.sc->var32), gld(&m.sc->sigma32), (float)m.lambda,
+                      (float)(m.pen_proc / m.S), ow);
 }
 
 }  // namespace mps

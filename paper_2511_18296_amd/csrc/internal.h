@@ -59,6 +59,19 @@ struct PeriodTables {
     RemEntry *rem_packed; // [T*S]
 };
 
+// The list pass's record of one block: everything a listed move of the block
+// reads, in one 64-byte line (the ore words too when S <= 256), so that a
+// move costs one line instead of a load from each of eight arrays.
+struct alignas(16) ListRec {
+    float c;           // (1/S) sum_s e_s v[s][b]
+    float rem;         // removal term of the block's current period
+    int32_t info;      // p | maxPred << 8 | minSucc << 16
+    float ton32, mb, Vb;
+    double ton64;
+    uint32_t ore[8];   // ore words 0..7 (S <= 256); larger S reads them from m.ore
+};
+static_assert(sizeof(ListRec) == 64, "one line per block");
+
 struct DevModel {
     int64_t N;
     int32_t S, T, W, nx, ny, nz;
@@ -94,9 +107,7 @@ struct DevModel {
     int32_t risk;
     double alpha;
     // list-mode per-block workspace
-    float *blk_c;          // [N] (1/S) sum_s e_s v[s][b]
-    float *blk_rem;        // [N] sum_s ore (removal clamp) for the current period
-    int32_t *blk_info;     // [N] p | maxPred << 8 | minSucc << 16
+    ListRec *blk_rec;      // [N] per-block record of the list pass
     uint32_t *tmark;       // [ceil(N/64)] tiles a move list touches; zero between calls
 };
 
