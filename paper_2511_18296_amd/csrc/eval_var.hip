@@ -81,22 +81,59 @@ __device__ __forceinline__ int32_t wsum_i(int32_t x) {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
     return x;
 }
+// Four sums over the wave at once: the four butterfly chains are independent,
+// so their shuffle latencies overlap.
+__device__ __forceinline__ void wsum4(float &a, float &b, float &c, double &d) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const float ya = __shfl_xor(a, o), yb = __shfl_xor(b, o), yc = __shfl_xor(c, o);
+        const double yd = __shfl_xor(d, o);
+        a += ya;
+        b += yb;
+        c += yc;
+        d += yd;
+    }
+}
+// Three integer sums at once (the counts of one radix round).
+__device__ __forceinline__ void wsum3i(int32_t &a, int32_t &b, int32_t &c) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t ya = __shfl_xor(a, o), yb = __shfl_xor(b, o), yc = __shfl_xor(c, o);
+        a += ya;
+        b += yb;
+        c += yc;
+    }
+}
 __device__ __forceinline__ uint32_t ord32(float x) {
     const uint32_t u = __float_as_uint(x);
     return (u >> 31) ? ~u : (u | 0x80000000u);
 }
 __device__ __forceinline__ double hinge_v(double x, double cap) { return x > cap ? x - cap : 0.0; }
 
+// What every destination of a block shares: its period, tonnage, precedence
+// window and the mining term of leaving its period.
+struct VarBlock {
+    int32_t pb, lo, hi;
+    double ton, am_rem;
+};
+__device__ __forceinline__ VarBlock var_block(const DevModel &m, const VarLds &L, int32_t b) {
+    VarBlock k;
+    k.pb = m.p[b];
+    k.ton = m.ton64[b];
+    prec_window(m, m.p, b, k.lo, k.hi);
+    k.am_rem = k.pb < m.T ? hinge_v(L.M[k.pb] - k.ton, m.mcap) - hinge_v(L.M[k.pb], m.mcap) : 0.0;
+    return k;
+}
+
 // Score and flags of the move (b, t) for the wave; v[q], ob (ore bit) of
-// this lane's scenarios s = lane + 64 q.
-__device__ __forceinline__ MoveOutVar score_var(const DevModel &m, const VarLds &L, int32_t b,
-                                                int32_t t, const float (&v)[kVQ],
-                                                const bool (&ob)[kVQ], int32_t NQ) {
+// this lane's scenarios s = lane + 64 q; kb the block's shared quantities.
+__device__ __forceinline__ MoveOutVar score_var(const DevModel &m, const VarLds &L,
+                                                const VarBlock &kb, int32_t t,
+                                                const float (&v)[kVQ], const bool (&ob)[kVQ],
+                                                int32_t NQ) {
     const int lane = threadIdx.x & 63;
     const int32_t S = m.S, T = m.T, T1 = m.T + 1;
     MoveOutVar o;
-    const int32_t pb = m.p[b];
-    const double ton = m.ton64[b];
+    const int32_t pb = kb.pb;
+    const double ton = kb.ton;
     float sd = 0.0f, sed = 0.0f, sdd = 0.0f;
     float ep[kVQ];
     double pacc = 0.0;
@@ -126,10 +163,7 @@ __device__ __forceinline__ MoveOutVar score_var(const DevModel &m, const VarLds 
             }
         }
     }
-    sd = wsum_f(sd);
-    sed = wsum_f(sed);
-    sdd = wsum_f(sdd);
-    pacc = wsum_d(pacc);
+    wsum4(sd, sed, sdd, pacc);
     viol = __ballot(viol) != 0ull;
     const float dmu = sd / S;
     float dr;
@@ -144,14 +178,22 @@ __device__ __forceinline__ MoveOutVar score_var(const DevModel &m, const VarLds 
             const int32_t s = lane + 64 * q;
             key[q] = (q < NQ && s < S) ? ord32(ep[q]) : 0xffffffffu;
         }
+        // two bits per round: the counts of keys below the three candidate
+        // prefixes pre | 01, pre | 10, pre | 11 of the round's bit pair
         uint32_t pre = 0u;
-        for (int bit = 31; bit >= 0; --bit) {
-            const uint32_t cand = pre | (1u << bit);
-            int32_t c = 0;
+        for (int bit = 30; bit >= 0; bit -= 2) {
+            const uint32_t c1 = pre | (1u << bit), c2 = pre | (2u << bit), c3 = pre | (3u << bit);
+            int32_t n1 = 0, n2 = 0, n3 = 0;
 #pragma unroll
             for (int q = 0; q < kVQ; ++q)
-                if (q < NQ) c += (key[q] < cand && lane + 64 * q < S) ? 1 : 0;
-            if (wsum_i(c) <= k - 1) pre = cand;
+                if (q < NQ && lane + 64 * q < S) {
+                    n1 += key[q] < c1 ? 1 : 0;
+                    n2 += key[q] < c2 ? 1 : 0;
+                    n3 += key[q] < c3 ? 1 : 0;
+                }
+            wsum3i(n1, n2, n3);
+            // the largest candidate with at most k - 1 keys below it
+            pre = n3 <= k - 1 ? c3 : n2 <= k - 1 ? c2 : n1 <= k - 1 ? c1 : pre;
         }
         // pre is the key of the k-th smallest value
         float xk = 0.0f, below = 0.0f;
@@ -190,9 +232,8 @@ __device__ __forceinline__ MoveOutVar score_var(const DevModel &m, const VarLds 
         am += hinge_v(Mt + ton, m.mcap) - hinge_v(Mt, m.mcap);
         mine_ok = Mt + ton <= m.mcap;
     }
-    if (pb < T) am += hinge_v(L.M[pb] - ton, m.mcap) - hinge_v(L.M[pb], m.mcap);
-    int32_t lo, hi;
-    prec_window(m, m.p, b, lo, hi);
+    am += kb.am_rem;
+    const int32_t lo = kb.lo, hi = kb.hi;
     const bool noop = t == pb;
     uint8_t f = 0;
     if (lo <= t && t <= hi) f |= MPS_PREC_OK;
@@ -254,8 +295,9 @@ __global__ void __launch_bounds__(kVT) k_eval_var_exh(DevModel m, int32_t D, flo
         float v[kVQ];
         bool ob[kVQ];
         var_column(m, (int32_t)b, NQ, v, ob);
+        const VarBlock kb = var_block(m, L, (int32_t)b);
         for (int32_t t = 0; t < D; ++t) {
-            const MoveOutVar o = score_var(m, L, (int32_t)b, t, v, ob, NQ);
+            const MoveOutVar o = score_var(m, L, kb, t, v, ob, NQ);
             if (lane == 0) {
                 const int64_t j = b * D + t;
                 score[j] = o.score;
@@ -294,7 +336,7 @@ __global__ void __launch_bounds__(kVT) k_eval_var_list(DevModel m, int64_t n, co
             float v[kVQ];
             bool ob[kVQ];
             var_column(m, b, NQ, v, ob);
-            o = score_var(m, L, b, t, v, ob, NQ);
+            o = score_var(m, L, var_block(m, L, b), t, v, ob, NQ);
         }
         if (lane == 0) {
             score[j] = o.score;

@@ -9,7 +9,7 @@
 // index), so the top k items are the k largest keys.  A most-significant-
 // digit radix select finds them:
 //   1. histogram of the top 11 bits over all items (every workgroup adds its
-//      LDS histogram to one of eight replicas);
+//      LDS histogram to one of four replicas);
 //   2. every workgroup of one more pass sums the replicas and picks the
 //      boundary digit (the same in all), then moves its items above the
 //      boundary digit to the output and items on it to a candidate buffer
@@ -38,7 +38,7 @@ constexpr int kRefineThreads = 1024;
 __constant__ int c_shift[kLevels] = {53, 42, 32, 21, 10, 0};
 __constant__ int c_bits[kLevels] = {11, 11, 10, 11, 11, 10};
 
-constexpr int kRep = 8;   // replicas of the level-0 histogram and counters
+constexpr int kRep = 4;   // replicas of the level-0 histogram and counters
 
 // Zero between calls (cleared by the refinement launch of each call, and by
 // the caller before the first call): the level-0 histogram replicas and the
@@ -257,16 +257,11 @@ __global__ void __launch_bounds__(256) k_compact0(const float *score, const uint
 // candidate is needed, and the chosen keys plus the remaining candidates are
 // exactly the top min(k, total) (keys are unique).
 constexpr int kRU = 8;   // candidates per thread in flight in the refinement
-// Up to this many candidates the refinement keeps them in LDS (two buffers of
-// the workgroup's dynamic LDS), so that each level reads and appends on chip;
-// more stay in the workspace's two global buffers.
-constexpr int kRefLds = 6144;
 __global__ void __launch_bounds__(kRefineThreads) k_refine(TopkWs w) {
     __shared__ uint32_t lh[kBins];
     __shared__ uint32_t part[256];
     __shared__ int32_t res[3];
     __shared__ int32_t n_src_s, n_dst_s, n_out_s, k_rem_s;
-    extern __shared__ __align__(16) uint64_t rbuf[];   // [2][kRefLds]
     const int tid = threadIdx.x;
     const TopkCtrl *c = w.ctrl;
     if (tid == 0) {
@@ -276,25 +271,6 @@ __global__ void __launch_bounds__(kRefineThreads) k_refine(TopkWs w) {
     }
     __syncthreads();
     uint64_t *src = w.cand0, *dst = w.cand1;
-    if (n_src_s <= kRefLds) {   // uniform
-        const int32_t ns = n_src_s;
-        for (int32_t c0 = 0; c0 < ns; c0 += kRU * kRefineThreads) {
-            uint64_t key[kRU];
-#pragma unroll
-            for (int u = 0; u < kRU; ++u) {
-                const int32_t i = c0 + tid + u * kRefineThreads;
-                key[u] = i < ns ? w.cand0[i] : 0ull;
-            }
-#pragma unroll
-            for (int u = 0; u < kRU; ++u) {
-                const int32_t i = c0 + tid + u * kRefineThreads;
-                if (i < ns) rbuf[i] = key[u];
-            }
-        }
-        src = rbuf;
-        dst = rbuf + kRefLds;
-        __syncthreads();
-    }
     for (int level = 1; level < kLevels; ++level) {
         const int32_t ns = n_src_s;
         // stop once every remaining candidate is needed
@@ -460,8 +436,7 @@ hipError_t launch_topk(const float *score, const uint8_t *flags, int64_t n, int3
                        w);
     hipLaunchKernelGGL(k_compact0, dim3((unsigned)g), dim3(256), 0, st, score, flags, n, req,
                        forbid, k, w);
-    hipLaunchKernelGGL(k_refine, dim3(1), dim3(kRefineThreads),
-                       sizeof(uint64_t) * 2 * (size_t)kRefLds, st, w);
+    hipLaunchKernelGGL(k_refine, dim3(1), dim3(kRefineThreads), 0, st, w);
     hipLaunchKernelGGL(k_rank, dim3((unsigned)((k + kRankKeys - 1) / kRankKeys)), dim3(256),
                        sizeof(uint64_t) * (size_t)((k + 31) & ~31), st, w, k, idx, top_score,
                        count);
