@@ -23,10 +23,16 @@
 // scenarios (each lane keeps its scenarios' v and ore bits in registers and
 // loops over the block's destinations).  A workgroup of four waves stages the
 // period tonnages (FP64), the discounted multipliers (FP32) and e_s in LDS and
-// then takes 64 blocks (or 64 listed moves).  The k-th smallest e'_s is found
-// by a bitwise radix select on the order-preserving integer image of the
-// FP32 values: 32 rounds of counting keys below a candidate prefix.
+// then takes 64 blocks (or 64 listed moves); what a block's destinations
+// share (its period, tonnage, precedence window, the mining term of leaving
+// its period) is formed once per block, and the four sums of a move are
+// reduced over the wave together.  The k-th smallest e'_s is found by a radix
+// select on the order-preserving integer image of the FP32 values: 16 rounds
+// of two bits, each counting the keys below three candidate prefixes with
+// ballots.
 #include <float.h>
+
+#include <type_traits>
 
 #include "internal.h"
 
@@ -93,15 +99,6 @@ __device__ __forceinline__ void wsum4(float &a, float &b, float &c, double &d) {
         d += yd;
     }
 }
-// Three integer sums at once (the counts of one radix round).
-__device__ __forceinline__ void wsum3i(int32_t &a, int32_t &b, int32_t &c) {
-    for (int o = 32; o > 0; o >>= 1) {
-        const int32_t ya = __shfl_xor(a, o), yb = __shfl_xor(b, o), yc = __shfl_xor(c, o);
-        a += ya;
-        b += yb;
-        c += yc;
-    }
-}
 __device__ __forceinline__ uint32_t ord32(float x) {
     const uint32_t u = __float_as_uint(x);
     return (u >> 31) ? ~u : (u | 0x80000000u);
@@ -113,9 +110,14 @@ __device__ __forceinline__ double hinge_v(double x, double cap) { return x > cap
 struct VarBlock {
     int32_t pb, lo, hi;
     double ton, am_rem;
+    float var32, sig32, cvar_e;   // the state's scalars (read once per workgroup)
 };
-__device__ __forceinline__ VarBlock var_block(const DevModel &m, const VarLds &L, int32_t b) {
+__device__ __forceinline__ VarBlock var_block(const DevModel &m, const VarLds &L, int32_t b,
+                                              const float (&scal)[3]) {
     VarBlock k;
+    k.var32 = scal[0];
+    k.sig32 = scal[1];
+    k.cvar_e = scal[2];
     k.pb = m.p[b];
     k.ton = m.ton64[b];
     prec_window(m, m.p, b, k.lo, k.hi);
@@ -124,10 +126,12 @@ __device__ __forceinline__ VarBlock var_block(const DevModel &m, const VarLds &L
 }
 
 // Score and flags of the move (b, t) for the wave; v[q], ob (ore bit) of
-// this lane's scenarios s = lane + 64 q; kb the block's shared quantities.
+// this lane's scenarios s = lane + 64 q (q < NQ <= Q); kb the block's shared
+// quantities.
+template <int Q>
 __device__ __forceinline__ MoveOutVar score_var(const DevModel &m, const VarLds &L,
                                                 const VarBlock &kb, int32_t t,
-                                                const float (&v)[kVQ], const bool (&ob)[kVQ],
+                                                const float (&v)[Q], const bool (&ob)[Q],
                                                 int32_t NQ) {
     const int lane = threadIdx.x & 63;
     const int32_t S = m.S, T = m.T, T1 = m.T + 1;
@@ -135,11 +139,11 @@ __device__ __forceinline__ MoveOutVar score_var(const DevModel &m, const VarLds 
     const int32_t pb = kb.pb;
     const double ton = kb.ton;
     float sd = 0.0f, sed = 0.0f, sdd = 0.0f;
-    float ep[kVQ];
+    float ep[Q];
     double pacc = 0.0;
     bool viol = false;
 #pragma unroll
-    for (int q = 0; q < kVQ; ++q) {
+    for (int q = 0; q < Q; ++q) {
         ep[q] = 0.0f;
         if (q >= NQ) break;
         const int32_t s = lane + 64 * q;
@@ -172,9 +176,9 @@ __device__ __forceinline__ MoveOutVar score_var(const DevModel &m, const VarLds 
         const double aS = m.alpha * S;
         int32_t k = (int32_t)ceil(aS);
         k = k < 1 ? 1 : (k > S ? S : k);
-        uint32_t key[kVQ];
+        uint32_t key[Q];
 #pragma unroll
-        for (int q = 0; q < kVQ; ++q) {
+        for (int q = 0; q < Q; ++q) {
             const int32_t s = lane + 64 * q;
             key[q] = (q < NQ && s < S) ? ord32(ep[q]) : 0xffffffffu;
         }
@@ -183,15 +187,16 @@ __device__ __forceinline__ MoveOutVar score_var(const DevModel &m, const VarLds 
         uint32_t pre = 0u;
         for (int bit = 30; bit >= 0; bit -= 2) {
             const uint32_t c1 = pre | (1u << bit), c2 = pre | (2u << bit), c3 = pre | (3u << bit);
+            // counts over the wave by ballot: no cross-lane round trip
             int32_t n1 = 0, n2 = 0, n3 = 0;
 #pragma unroll
-            for (int q = 0; q < kVQ; ++q)
-                if (q < NQ && lane + 64 * q < S) {
-                    n1 += key[q] < c1 ? 1 : 0;
-                    n2 += key[q] < c2 ? 1 : 0;
-                    n3 += key[q] < c3 ? 1 : 0;
+            for (int q = 0; q < Q; ++q)
+                if (q < NQ) {
+                    const bool in = lane + 64 * q < S;
+                    n1 += __popcll(__ballot(in && key[q] < c1));
+                    n2 += __popcll(__ballot(in && key[q] < c2));
+                    n3 += __popcll(__ballot(in && key[q] < c3));
                 }
-            wsum3i(n1, n2, n3);
             // the largest candidate with at most k - 1 keys below it
             pre = n3 <= k - 1 ? c3 : n2 <= k - 1 ? c2 : n1 <= k - 1 ? c1 : pre;
         }
@@ -200,7 +205,7 @@ __device__ __forceinline__ MoveOutVar score_var(const DevModel &m, const VarLds 
         int32_t nb = 0;
         bool hk = false;
 #pragma unroll
-        for (int q = 0; q < kVQ; ++q) {
+        for (int q = 0; q < Q; ++q) {
             if (q >= NQ || lane + 64 * q >= S) continue;
             if (key[q] < pre) {
                 below += ep[q];
@@ -216,9 +221,9 @@ __device__ __forceinline__ MoveOutVar score_var(const DevModel &m, const VarLds 
         const uint64_t has = __ballot(hk);
         xk = __shfl(xk, __ffsll((unsigned long long)has) - 1);
         const float cv = (below + (float)(k - 1 - nb) * xk + (float)(aS - (k - 1)) * xk) / (float)aS;
-        dr = (1.0f - (float)m.lambda) * dmu + (float)m.lambda * (cv - (float)m.sc->cvar_e);
+        dr = (1.0f - (float)m.lambda) * dmu + (float)m.lambda * (cv - kb.cvar_e);
     } else {
-        const float var32 = m.sc->var32, sig32 = m.sc->sigma32;
+        const float var32 = kb.var32, sig32 = kb.sig32;
         const float dvar = 2.0f * sed / S + sdd / S - dmu * dmu;
         const float vp = fmaxf(var32 + dvar, 0.0f);
         const float den = sqrtf(vp) + sig32;
@@ -264,11 +269,12 @@ __device__ __forceinline__ void var_stage(const DevModel &m, const VarLds &L) {
     __syncthreads();
 }
 
+template <int Q>
 __device__ __forceinline__ void var_column(const DevModel &m, int32_t b, int32_t NQ,
-                                           float (&v)[kVQ], bool (&ob)[kVQ]) {
+                                           float (&v)[Q], bool (&ob)[Q]) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int q = 0; q < kVQ; ++q) {
+    for (int q = 0; q < Q; ++q) {
         v[q] = 0.0f;
         ob[q] = false;
         if (q >= NQ) continue;
@@ -279,6 +285,7 @@ __device__ __forceinline__ void var_column(const DevModel &m, int32_t b, int32_t
     }
 }
 
+template <int Q>
 __global__ void __launch_bounds__(kVT) k_eval_var_exh(DevModel m, int32_t D, float *score,
                                                       uint8_t *flags, float *dR, float *dPp,
                                                       float *dPm) {
@@ -288,16 +295,17 @@ __global__ void __launch_bounds__(kVT) k_eval_var_exh(DevModel m, int32_t D, flo
     var_stage(m, L);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t NQ = (m.S + 63) / 64;
+    const float scal[3] = {gld(&m.sc->var32), gld(&m.sc->sigma32), (float)gld(&m.sc->cvar_e)};
     const int64_t b0 = (int64_t)blockIdx.x * kVItems;
     for (int i = wave; i < kVItems; i += kVW) {
         const int64_t b = b0 + i;
         if (b >= m.N) break;
-        float v[kVQ];
-        bool ob[kVQ];
-        var_column(m, (int32_t)b, NQ, v, ob);
-        const VarBlock kb = var_block(m, L, (int32_t)b);
+        float v[Q];
+        bool ob[Q];
+        var_column<Q>(m, (int32_t)b, NQ, v, ob);
+        const VarBlock kb = var_block(m, L, (int32_t)b, scal);
         for (int32_t t = 0; t < D; ++t) {
-            const MoveOutVar o = score_var(m, L, kb, t, v, ob, NQ);
+            const MoveOutVar o = score_var<Q>(m, L, kb, t, v, ob, NQ);
             if (lane == 0) {
                 const int64_t j = b * D + t;
                 score[j] = o.score;
@@ -312,6 +320,7 @@ __global__ void __launch_bounds__(kVT) k_eval_var_exh(DevModel m, int32_t D, flo
     }
 }
 
+template <int Q>
 __global__ void __launch_bounds__(kVT) k_eval_var_list(DevModel m, int64_t n, const int32_t *blk,
                                                        const int8_t *per, float *score,
                                                        uint8_t *flags, float *dR, float *dPp,
@@ -322,6 +331,7 @@ __global__ void __launch_bounds__(kVT) k_eval_var_list(DevModel m, int64_t n, co
     var_stage(m, L);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t NQ = (m.S + 63) / 64;
+    const float scal[3] = {gld(&m.sc->var32), gld(&m.sc->sigma32), (float)gld(&m.sc->cvar_e)};
     const int64_t i0 = (int64_t)blockIdx.x * kVItems;
     for (int i = wave; i < kVItems; i += kVW) {
         const int64_t j = i0 + i;
@@ -333,10 +343,10 @@ __global__ void __launch_bounds__(kVT) k_eval_var_list(DevModel m, int64_t n, co
             o.flags = MPS_BAD;
             o.dr = o.dpp = o.dpm = 0.0f;
         } else {
-            float v[kVQ];
-            bool ob[kVQ];
-            var_column(m, b, NQ, v, ob);
-            o = score_var(m, L, var_block(m, L, b), t, v, ob, NQ);
+            float v[Q];
+            bool ob[Q];
+            var_column<Q>(m, b, NQ, v, ob);
+            o = score_var<Q>(m, L, var_block(m, L, b, scal), t, v, ob, NQ);
         }
         if (lane == 0) {
             score[j] = o.score;
@@ -355,16 +365,26 @@ size_t eval_var_lds_bytes(const DevModel &m) { return var_layout(m.S, m.T, nullp
 hipError_t launch_eval_var(const DevModel &m, const mps_moves &mv, float *score, uint8_t *flags,
                            float *dR, float *dPp, float *dPm, hipStream_t st) {
     const size_t lds = eval_var_lds_bytes(m);
-    if (mv.exhaustive) {
-        const int32_t D = mv.include_never ? m.T + 1 : m.T;
-        const unsigned g = (unsigned)((m.N + kVItems - 1) / kVItems);
-        hipLaunchKernelGGL(k_eval_var_exh, dim3(g), dim3(kVT), lds, st, m, D, score, flags, dR,
-                           dPp, dPm);
-    } else if (mv.n > 0) {
-        const unsigned g = (unsigned)((mv.n + kVItems - 1) / kVItems);
-        hipLaunchKernelGGL(k_eval_var_list, dim3(g), dim3(kVT), lds, st, m, mv.n, mv.block,
-                           mv.period, score, flags, dR, dPp, dPm);
-    }
+    // registers for the scenarios a lane holds: 64, 128, 256, 512 or 1024 per wave
+    const int32_t nq = (m.S + 63) / 64;
+    auto go = [&](auto qtag) {
+        constexpr int Q = decltype(qtag)::value;
+        if (mv.exhaustive) {
+            const int32_t D = mv.include_never ? m.T + 1 : m.T;
+            const unsigned g = (unsigned)((m.N + kVItems - 1) / kVItems);
+            hipLaunchKernelGGL(k_eval_var_exh<Q>, dim3(g), dim3(kVT), lds, st, m, D, score, flags,
+                               dR, dPp, dPm);
+        } else if (mv.n > 0) {
+            const unsigned g = (unsigned)((mv.n + kVItems - 1) / kVItems);
+            hipLaunchKernelGGL(k_eval_var_list<Q>, dim3(g), dim3(kVT), lds, st, m, mv.n,
+                               mv.block, mv.period, score, flags, dR, dPp, dPm);
+        }
+    };
+    if (nq <= 1) go(std::integral_constant<int, 1>());
+    else if (nq <= 2) go(std::integral_constant<int, 2>());
+    else if (nq <= 4) go(std::integral_constant<int, 4>());
+    else if (nq <= 8) go(std::integral_constant<int, 8>());
+    else go(std::integral_constant<int, kVQ>());
     return hipGetLastError();
 }
 
