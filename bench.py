@@ -78,14 +78,22 @@ def eval_bytes(N, S, T, D):
 
 
 def cpu_model():
+    """The host CPU as /proc/cpuinfo describes its first logical CPU: model
+    name, then family/model/stepping, clock and cache size where given."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break   # the first logical CPU only
+                k, _, v = line.partition(":")
+                fields[k.strip()] = v.strip()
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    name = fields.get("model name", "unknown")
+    extra = [f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping", "cpu MHz",
+                                          "cache size") if k in fields]
+    return name + (" (" + ", ".join(extra) + ")" if extra else "")
 
 
 def cpu_baseline(inst, k, min_seconds=10.0, max_reps=200):
