@@ -205,3 +205,51 @@ def test_phased_topk_selection_paths(case):
             np.testing.assert_array_equal(to_np(b.top_idx[i])[:c], ri)
             np.testing.assert_array_equal(to_np(b.top_score[i])[:c], rs.astype(np.float32))
         b.close()
+
+
+def test_phased_lists_changed_after_create_stay_exact(phased):
+    """The block order of the move lists is computed when the batch is built;
+    lists that change afterwards (in place, same lengths) are still scored
+    exactly, each move at its own position (only the locality is lost), and
+    a retune recomputes the order with the same results."""
+    from paper_2511_18296_amd.binding import MoveSet
+    insts, moves, models, dev, batch, k = phased
+    rng = np.random.default_rng(77)
+    saved = [(b.clone(), p.clone()) for b, p in dev]
+    try:
+        for (b, p), inst in zip(dev, insts):
+            n = b.shape[0]
+            if n == 0:
+                continue
+            nb = rng.integers(0, inst.N, n).astype(np.int32)
+            npd = rng.integers(0, inst.T + 1, n).astype(np.int8)
+            b.copy_(torch.from_numpy(nb))
+            p.copy_(torch.from_numpy(npd))
+        torch.cuda.synchronize()
+        for attempt in ("unchanged order", "after retune"):
+            if attempt == "after retune":
+                _retune_each(batch, len(models))
+            _say(f"run with changed lists ({attempt})")
+            batch.run()
+            out = _outputs(batch)
+            for i, inst in enumerate(insts):
+                sc, fl, ti, ts, cnt = out[i]
+                ssc, sfl = models[i].eval_moves(MoveSet(False, True, dev[i][0], dev[i][1]))
+                np.testing.assert_array_equal(to_np(sfl), fl, err_msg=f"model {i} {attempt}")
+                np.testing.assert_array_equal(to_np(ssc), sc, err_msg=f"model {i} {attempt}")
+                ri, rs = oracle.topk(sc, fl, k)
+                assert cnt == len(ri)
+                np.testing.assert_array_equal(ti[:cnt], ri)
+    finally:
+        for (b, p), (b0, p0) in zip(dev, saved):
+            b.copy_(b0)
+            p.copy_(p0)
+        torch.cuda.synchronize()
+        _retune_each(batch, len(models))
+
+
+def _retune_each(batch, n):
+    # every model keeps its tuning; setting it recomputes its block order
+    for i in range(n):
+        t = batch.tuning(i)
+        batch.set_tuning(t["tiles_per_item"], t["moves_per_item"], t["rows"], i=i)

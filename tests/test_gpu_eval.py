@@ -63,6 +63,33 @@ def test_eval_list_paper_scale():
     print(f"paper-scale list: max score error {err:.3g}")
 
 
+def test_eval_short_lists_on_disjoint_tiles():
+    """Short lists (fewer than eight moves per 64-block tile) mark the tiles
+    they touch and the block pass skips the rest: consecutive short lists on
+    disjoint and overlapping tile sets of one model, each against the oracle,
+    then a long list (all tiles) and a short one again."""
+    from paper_2511_18296_amd.binding import MoveSet
+    inst = instance("paper")
+    m = gpu_model(inst)
+    o = oracle.Oracle(inst)
+    mu = o.objective(inst.p0)["mu"]
+    rng = np.random.default_rng(31)
+    tiles = (inst.N + 63) // 64
+    cases = []
+    for lo, hi, n in ((0, tiles // 3, 700), (tiles // 3, 2 * tiles // 3, 300),
+                      (tiles // 4, tiles // 2, 1000), (0, tiles, 9 * tiles),
+                      (2 * tiles // 3, tiles, 50)):
+        blk = rng.integers(lo * 64, min(inst.N, hi * 64), n).astype(np.int32)
+        per = rng.integers(0, inst.T + 1, n).astype(np.int8)
+        cases.append((blk, per))
+    for j, (blk, per) in enumerate(cases):
+        mv = MoveSet(False, True, torch.from_numpy(blk).cuda(), torch.from_numpy(per).cuda())
+        sc, fl = m.eval_moves(mv)
+        osc, ofl = o.eval_moves(inst.p0, block=blk, period=per)
+        np.testing.assert_array_equal(to_np(fl), ofl, err_msg=f"list {j}")
+        compare_scores(to_np(sc), osc, ofl, mu, f"list {j}")
+
+
 def test_eval_list_empty():
     from paper_2511_18296_amd.binding import MoveSet
     inst = instance("tiny")
