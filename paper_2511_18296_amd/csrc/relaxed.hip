@@ -1176,71 +1176,6 @@ hipError_t launch_relaxed_bwd(const DevModel &m, const float *x, const mps_relax
     return hipGetLastError();
 }
 
-// ---- gradient ranking ---------------------------------------------------------------
-// gain(b,t') = Gc[b,p_b] - Gc[b,t'], Gc[b,t] = sum_{u<t} dJ/dx[b,u] (FP64 prefix
-// sums): the first-order change of J for moving b from p_b to t'.  No-op moves
-// get flag 0 so that the top-k (require 1) skips them.
-__global__ void k_rank_gains(DevModel m, const float *grad, float *gain, uint8_t *fl) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= m.N) return;
-    const int32_t T = m.T, D = T + 1;
-    const int32_t pb = m.p[b];
-    double gpb = 0.0;
-    {
-        double run = 0.0;
-        for (int32_t t = 0; t < D; ++t) {
-            if (t == pb) gpb = run;
-            if (t < T) run += (double)grad[b * T + t];
-        }
-    }
-    // only moves that keep the schedule precedence-feasible (Eq. 15) rank:
-    // the repair could never apply the others
-    int32_t lo, hi;
-    prec_window(m, m.p, (int32_t)b, lo, hi);
-    double run = 0.0;
-    for (int32_t t = 0; t < D; ++t) {
-        gain[b * D + t] = (float)(gpb - run);
-        fl[b * D + t] = (t != pb && lo <= t && t <= hi) ? 1 : 0;
-        if (t < T) run += (double)grad[b * T + t];
-    }
-}
-
-__global__ void k_rank_decode(int32_t D, const int64_t *idx, int32_t k, int32_t *blk, int8_t *per) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= k) return;
-    const int64_t id = idx[i];
-    blk[i] = id >= 0 ? (int32_t)(id / D) : -1;
-    per[i] = id >= 0 ? (int8_t)(id % D) : (int8_t)-1;
-}
-
-size_t rank_ws_bytes(const DevModel &m, int32_t k) {
-    const int64_t n = m.N * (m.T + 1);
-    return al256(4 * (size_t)n) + al256((size_t)n) + al256(8 * (size_t)k) + topk_ws_bytes(n, k);
-}
-
-hipError_t launch_rank(const DevModel &m, const float *grad, int32_t k, int32_t *blk, int8_t *per,
-                       float *gain_out, int32_t *count, void *ws, hipStream_t st) {
-    const int64_t n = m.N * (m.T + 1);
-    char *c = (char *)ws;
-    float *gain = (float *)c;
-    c += al256(4 * (size_t)n);
-    uint8_t *fl = (uint8_t *)c;
-    c += al256((size_t)n);
-    int64_t *idx = (int64_t *)c;
-    c += al256(8 * (size_t)k);
-    hipLaunchKernelGGL(k_rank_gains, dim3((unsigned)((m.N + 255) / 256)), dim3(256), 0, st, m,
-                       grad, gain, fl);
-    hipError_t e = launch_topk(gain, fl, n, k, 1, 0, idx, gain_out, count, c, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rank_decode, dim3((k + 255) / 256), dim3(256), 0, st, m.T + 1, idx, k,
-                       blk, per);
-    return hipGetLastError();
-}
-
-}  // namespace mps
-
-namespace mps {
-
 // x(p)[b,t] = [t >= p_b]: the integer point of the current schedule.
 __global__ void k_integer_x(DevModel m, float *x) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
