@@ -305,9 +305,9 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     uint32_t *ore_, *full_add, *full_rem;
     double *ton64, *mb64, *Vb64, *Ns, *O, *M, *d64;
     int8_t *p;
-    int32_t *tcnt, *trng;
-    AddEntry *ladd, *padd;
-    RemEntry *lrem, *prem;
+    int32_t *trng;
+    AddEntry *padd;
+    RemEntry *prem;
     DevScalars *sc;
 #define ALLOC(ptr, cnt)                      \
     if ((st = m->alloc(ptr, cnt)) != MPS_OK) { \
@@ -339,8 +339,7 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
                      o_O = take(8 * (size_t)T * S), o_M = take(8 * (size_t)T),
                      o_e = take(4 * ((size_t)S + 64)), o_sc = take(sizeof(DevScalars)),
                      o_fa = take(4 * (size_t)T * W), o_fr = take(4 * (size_t)T * W),
-                     o_cnt = take(8 * (size_t)T), o_la = take(sizeof(AddEntry) * (size_t)T * S),
-                     o_lr = take(sizeof(RemEntry) * (size_t)T * S), o_rg = take(16 * (size_t)T),
+                     o_rg = take(16 * (size_t)T),
                      o_pa = take(sizeof(AddEntry) * (size_t)T * S),
                      o_pr = take(sizeof(RemEntry) * (size_t)T * S);
         char *arena = nullptr;
@@ -355,9 +354,6 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
         sc = (DevScalars *)(arena + o_sc);
         full_add = (uint32_t *)(arena + o_fa);
         full_rem = (uint32_t *)(arena + o_fr);
-        tcnt = (int32_t *)(arena + o_cnt);
-        ladd = (AddEntry *)(arena + o_la);
-        lrem = (RemEntry *)(arena + o_lr);
         trng = (int32_t *)(arena + o_rg);
         padd = (AddEntry *)(arena + o_pa);
         prem = (RemEntry *)(arena + o_pr);
@@ -421,9 +417,6 @@ mps_status mps_build_model(const mps_params *prm, const float *v, const uint32_t
     d.d64 = d64;
     d.tab.full_add = full_add;
     d.tab.full_rem = full_rem;
-    d.tab.cnt = tcnt;
-    d.tab.add = ladd;
-    d.tab.rem = lrem;
     d.tab.rng = trng;
     d.tab.add_packed = padd;
     d.tab.rem_packed = prem;

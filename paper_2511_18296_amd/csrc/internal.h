@@ -38,7 +38,8 @@ struct DevScalars {
 //     full rem    : O - cap >= ton_max               -> -ton_b (bit in full_rem)
 //     partial rem : 0 < O - cap < ton_max            -> list entry a = O - cap,
 //                   value -min(a, ton_b)
-// Lists are per period, scenario-ascending, entry j of period t at [t*S + j].
+// Lists are per period and scenario-ascending, concatenated over the periods
+// in order; rng gives each period's range.
 struct AddEntry {
     double tau;
     float d;
@@ -51,9 +52,6 @@ struct RemEntry {
 struct PeriodTables {
     uint32_t *full_add;   // [T][W] bit s%32 of word s/32
     uint32_t *full_rem;   // [T][W]
-    int32_t *cnt;         // [2][T] list lengths per period (add, rem)
-    AddEntry *add;        // [T][S] per-period slots (written by the table kernel)
-    RemEntry *rem;        // [T][S]
     int32_t *rng;         // [4][T]: packed add begin/end, rem begin/end
     AddEntry *add_packed; // [T*S] concatenated lists
     RemEntry *rem_packed; // [T*S]

@@ -179,6 +179,25 @@ hipError_t launch_set_schedule(const DevModel &m, const int8_t *p_in,
 }
 
 // ---- statistics and penalty tables from (N_s, O, M) ------------------------
+// One launch of two workgroups of kPT threads.
+//
+// Workgroup 0, the scalars: mu, var, sigma, e_s and the objective terms.  N_s
+// and the M entries are staged in LDS while the processing-excess terms are
+// summed, so that all their loads are in flight together.  Every sum is a
+// fixed-order tree whose leaves are the strided partial sums of threads
+// 0..255; the other threads add zeros, which changes no partial sum.
+//
+// Workgroup 1, the penalty tables of every period.  The items (t, s), t < T,
+// s < S, in period-major order; a packed list is the order-preserving
+// compaction of the items by "partial add" (or "partial rem"), so each
+// period's entries are contiguous and scenario-ascending, periods in order.
+// The items are cut into jobs of 64 scenarios of one period, one job per wave
+// at a time: a first pass counts each job's partial entries (and writes its
+// words of the full-bit tables), a scan over the jobs gives each job's output
+// offsets, and a second pass writes the entries and the period ranges.
+constexpr int kPT = 1024;
+constexpr int kPW = kPT / 64;
+
 __device__ double block_sum_f64(double x, double *red) {
     // fixed-order tree over blockDim.x (power of two) threads
     const int tid = threadIdx.x;
@@ -192,6 +211,25 @@ __device__ double block_sum_f64(double x, double *red) {
     double r = red[0];
     __syncthreads();
     return r;
+}
+
+// Two such trees at once (red holds 2 * blockDim.x entries).
+__device__ void block_sum2_f64(double &x, double &y, double *red) {
+    const int tid = threadIdx.x, n = blockDim.x;
+    __syncthreads();
+    red[tid] = x;
+    red[n + tid] = y;
+    __syncthreads();
+    for (int w = n / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            red[tid] += red[tid + w];
+            red[n + tid] += red[n + tid + w];
+        }
+        __syncthreads();
+    }
+    x = red[0];
+    y = red[n];
+    __syncthreads();
 }
 
 // Smallest non-negative double x with O + x > cap in FP64 arithmetic (the sum
@@ -209,82 +247,98 @@ __device__ double min_exceeding(double O, double cap, double hi) {
     return __longlong_as_double((long long)hi_b);
 }
 
-// Block T: mu, var, sigma, e_s and the objective terms.  Blocks t < T: the
-// penalty tables of period t.  256 threads.
-__global__ void __launch_bounds__(256) k_prep(DevModel m) {
-    __shared__ double red[256];
-    __shared__ int32_t woff[4];
+__device__ void prep_scalars(const DevModel &m, double *red, double *nsl, double *ml) {
     const int tid = threadIdx.x;
-    const int32_t S = m.S, T = m.T, W = m.W;
-    const int32_t t = blockIdx.x;
-    if (t == T) {
-        double s = 0.0;
-        for (int32_t i = tid; i < S; i += 256) s += m.Ns[i];
-        double mu = block_sum_f64(s, red) / S;
-        double q = 0.0;
+    const int32_t S = m.S, T = m.T;
+    const bool act = tid < 256;
+    for (int32_t i = tid; i < S; i += kPT) nsl[i] = m.Ns[i];
+    if (tid < T) ml[tid] = m.M[tid];   // T < kPT
+    double pp = 0.0;
+    if (act)
+        for (int64_t i = tid; i < (int64_t)S * T; i += 256) pp += hinge64(m.O[i], m.pcap);
+    __syncthreads();
+    double s = 0.0;
+    if (act)
+        for (int32_t i = tid; i < S; i += 256) s += nsl[i];
+    block_sum2_f64(s, pp, red);
+    const double mu = s / S;
+    double q = 0.0;
+    if (act)
         for (int32_t i = tid; i < S; i += 256) {
-            double e = m.Ns[i] - mu;
+            const double e = nsl[i] - mu;
             q += e * e;
         }
-        double var = block_sum_f64(q, red) / S;
-        double pp = 0.0;
-        for (int64_t i = tid; i < (int64_t)S * T; i += 256) pp += hinge64(m.O[i], m.pcap);
-        pp = block_sum_f64(pp, red);
-        for (int32_t i = tid; i < S; i += 256) m.e32[i] = (float)(m.Ns[i] - mu);
-        // CVaR of the lower alpha tail: scenario i of rank r (value, then
-        // index) weighs 1 below rank k-1, alpha*S - k + 1 at rank k-1
-        double cv = 0.0;
-        const double aS = m.alpha * S;
-        int32_t kq = (int32_t)ceil(aS);
-        kq = kq < 1 ? 1 : (kq > S ? S : kq);
-        if (m.risk == 1) {
-            double part = 0.0;
+    const double var = block_sum_f64(q, red) / S;
+    for (int32_t i = tid; i < S; i += kPT) m.e32[i] = (float)(nsl[i] - mu);
+    // CVaR of the lower alpha tail: scenario i of rank r (value, then index)
+    // weighs 1 below rank k-1, alpha*S - k + 1 at rank k-1
+    double cv = 0.0;
+    const double aS = m.alpha * S;
+    int32_t kq = (int32_t)ceil(aS);
+    kq = kq < 1 ? 1 : (kq > S ? S : kq);
+    if (m.risk == 1) {
+        double part = 0.0;
+        if (act)
             for (int32_t i = tid; i < S; i += 256) {
-                const double x = m.Ns[i];
+                const double x = nsl[i];
                 int32_t r = 0;
                 for (int32_t j = 0; j < S; ++j) {
-                    const double y = m.Ns[j];
+                    const double y = nsl[j];
                     r += (y < x || (y == x && j < i)) ? 1 : 0;
                 }
                 if (r < kq - 1) part += x;
                 else if (r == kq - 1) part += (aS - (kq - 1)) * x;
             }
-            cv = block_sum_f64(part, red) / aS;
-        }
-        if (tid == 0) {
-            double pm = 0.0;
-            for (int32_t u = 0; u < T; ++u) pm += hinge64(m.M[u], m.mcap);
-            double sigma = sqrt(var);
-            DevScalars *sc = m.sc;
-            sc->mu = mu;
-            sc->var = var;
-            sc->sigma = sigma;
-            sc->sigma32 = (float)sigma;
-            sc->var32 = (float)var;
-            sc->cvar_e = m.risk == 1 ? cv - mu : 0.0;
-            sc->R = m.risk == 1 ? mu - m.lambda * (mu - cv) : mu - m.lambda * sigma;
-            sc->Pp = m.pen_proc * pp / S;
-            sc->Pm = m.pen_mine * pm;
-            sc->J = sc->R - sc->Pp - sc->Pm;
-        }
-        return;
+        cv = block_sum_f64(part, red) / aS;
     }
-    // tables of period t
-    const int lane = tid & 63, wave = tid >> 6;
-    int32_t base_add = 0, base_rem = 0;
-    for (int32_t s0 = 0; s0 < S; s0 += 256) {
-        const int32_t s = s0 + tid;
-        const bool in = s < S;
-        const double O = in ? m.O[(int64_t)t * S + s] : 0.0;
-        const bool full_add = in && O >= m.pcap && O + m.ton_min > m.pcap;
-        const bool part_add = in && !full_add && O + m.ton_max > m.pcap;
-        const double a = O - m.pcap;
-        const bool full_rem = in && a >= m.ton_max;
-        const bool part_rem = in && !full_rem && a > 0.0;
-        const uint64_t bfa = __ballot(full_add), bfr = __ballot(full_rem);
-        const uint64_t bpa = __ballot(part_add), bpr = __ballot(part_rem);
+    if (tid == 0) {
+        double pm = 0.0;
+        for (int32_t u = 0; u < T; ++u) pm += hinge64(ml[u], m.mcap);
+        double sigma = sqrt(var);
+        DevScalars *sc = m.sc;
+        sc->mu = mu;
+        sc->var = var;
+        sc->sigma = sigma;
+        sc->sigma32 = (float)sigma;
+        sc->var32 = (float)var;
+        sc->cvar_e = m.risk == 1 ? cv - mu : 0.0;
+        sc->R = m.risk == 1 ? mu - m.lambda * (mu - cv) : mu - m.lambda * sigma;
+        sc->Pp = m.pen_proc * pp / S;
+        sc->Pm = m.pen_mine * pm;
+        sc->J = sc->R - sc->Pp - sc->Pm;
+    }
+}
+
+struct PrepItem {
+    double O;
+    bool full_add, part_add, full_rem, part_rem;
+};
+
+__device__ __forceinline__ PrepItem prep_item(const DevModel &m, int32_t t, int32_t s) {
+    PrepItem k;
+    const bool in = s < m.S;
+    k.O = in ? m.O[(int64_t)t * m.S + s] : 0.0;
+    k.full_add = in && k.O >= m.pcap && k.O + m.ton_min > m.pcap;
+    k.part_add = in && !k.full_add && k.O + m.ton_max > m.pcap;
+    const double a = k.O - m.pcap;
+    k.full_rem = in && a >= m.ton_max;
+    k.part_rem = in && !k.full_rem && a > 0.0;
+    return k;
+}
+
+__device__ void prep_tables(const DevModel &m, uint64_t *jc) {
+    __shared__ uint64_t wt[kPW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int32_t S = m.S, T = m.T, W = m.W;
+    const int32_t nc = (S + 63) / 64, J = T * nc;
+    // pass 1: per job, the counts (add in the low half, rem in the high half)
+    for (int32_t j = wave; j < J; j += kPW) {
+        const int32_t t = j / nc, c = j - t * nc;
+        const PrepItem k = prep_item(m, t, 64 * c + lane);
+        const uint64_t bfa = __ballot(k.full_add), bfr = __ballot(k.full_rem);
+        const uint64_t bpa = __ballot(k.part_add), bpr = __ballot(k.part_rem);
         if (lane == 0) {
-            const int32_t w0 = (s0 >> 5) + wave * 2;   // 64 scenarios = 2 words
+            const int32_t w0 = 2 * c;   // 64 scenarios = 2 words
             if (w0 < W) {
                 m.tab.full_add[(int64_t)t * W + w0] = (uint32_t)bfa;
                 m.tab.full_rem[(int64_t)t * W + w0] = (uint32_t)bfr;
@@ -293,81 +347,83 @@ __global__ void __launch_bounds__(256) k_prep(DevModel m) {
                 m.tab.full_add[(int64_t)t * W + w0 + 1] = (uint32_t)(bfa >> 32);
                 m.tab.full_rem[(int64_t)t * W + w0 + 1] = (uint32_t)(bfr >> 32);
             }
+            jc[j] = (uint64_t)__popcll(bpa) | ((uint64_t)__popcll(bpr) << 32);
         }
-        // order-preserving compaction of the partial scenarios
-        __syncthreads();
-        if (lane == 0) woff[wave] = (int32_t)__popcll(bpa) | ((int32_t)__popcll(bpr) << 16);
-        __syncthreads();
-        int32_t oa = base_add, orr = base_rem, ta = 0, tr = 0;
-        for (int w = 0; w < 4; ++w) {
-            const int32_t ca = woff[w] & 0xffff, cr = woff[w] >> 16;
-            if (w < wave) {
-                oa += ca;
-                orr += cr;
-            }
-            ta += ca;
-            tr += cr;
-        }
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        if (part_add) {
-            const int32_t j = oa + (int32_t)__popcll(bpa & below);
+    }
+    __syncthreads();
+    // exclusive scan of the job counts: thread tid owns jobs [j0, j1); both
+    // halves scan at once (each total is below 2^32, so no carry crosses)
+    const int32_t E = (J + kPT - 1) / kPT;
+    const int32_t j0 = min(J, tid * E), j1 = min(J, j0 + E);
+    uint64_t own = 0;
+    for (int32_t j = j0; j < j1; ++j) own += jc[j];
+    uint64_t x = own;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wt[wave] = x;
+    __syncthreads();
+    uint64_t run = x - own, tot = 0;
+    for (int w = 0; w < kPW; ++w) {
+        if (w < wave) run += wt[w];
+        tot += wt[w];
+    }
+    for (int32_t j = j0; j < j1; ++j) {
+        const uint64_t c = jc[j];
+        jc[j] = run;
+        run += c;
+    }
+    __syncthreads();
+    // pass 2: the entries at their offsets, and the period ranges
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int32_t j = wave; j < J; j += kPW) {
+        const int32_t t = j / nc, c = j - t * nc, s = 64 * c + lane;
+        const PrepItem k = prep_item(m, t, s);
+        const uint64_t bpa = __ballot(k.part_add), bpr = __ballot(k.part_rem);
+        const uint64_t base = jc[j];
+        const int32_t ba = (int32_t)(uint32_t)base, br = (int32_t)(base >> 32);
+        if (k.part_add) {
             AddEntry e;
-            e.tau = min_exceeding(O, m.pcap, 2.0 * m.ton_max);
-            e.d = (float)(m.pcap - O);
+            e.tau = min_exceeding(k.O, m.pcap, 2.0 * m.ton_max);
+            e.d = (float)(m.pcap - k.O);
             e.s = s;
-            m.tab.add[(int64_t)t * S + j] = e;
+            m.tab.add_packed[ba + (int32_t)__popcll(bpa & below)] = e;
         }
-        if (part_rem) {
-            const int32_t j = orr + (int32_t)__popcll(bpr & below);
+        if (k.part_rem) {
             RemEntry e;
-            e.a = (float)a;
+            e.a = (float)(k.O - m.pcap);
             e.s = s;
-            m.tab.rem[(int64_t)t * S + j] = e;
+            m.tab.rem_packed[br + (int32_t)__popcll(bpr & below)] = e;
         }
-        base_add += ta;
-        base_rem += tr;
-        __syncthreads();
+        if (c == 0 && lane == 0) {
+            m.tab.rng[t] = ba;
+            m.tab.rng[2 * T + t] = br;
+            if (t > 0) {
+                m.tab.rng[T + t - 1] = ba;
+                m.tab.rng[3 * T + t - 1] = br;
+            }
+        }
     }
     if (tid == 0) {
-        m.tab.cnt[t] = base_add;
-        m.tab.cnt[T + t] = base_rem;
+        m.tab.rng[2 * T - 1] = (int32_t)(uint32_t)tot;
+        m.tab.rng[4 * T - 1] = (int32_t)(tot >> 32);
     }
 }
 
-// Concatenate the per-period partial lists (CSR): rng[0..T) add begin,
-// rng[T..2T) add end, rng[2T..3T) rem begin, rng[3T..4T) rem end.  One
-// workgroup of 256 threads.
-__global__ void __launch_bounds__(256) k_pack_tables(DevModel m) {
-    __shared__ int32_t off[2][MPS_MAX_PERIODS + 1];
-    const int tid = threadIdx.x;
-    const int32_t T = m.T, S = m.S;
-    if (tid < 2) {
-        int32_t run = 0;
-        for (int32_t t = 0; t < T; ++t) {
-            off[tid][t] = run;
-            run += m.tab.cnt[tid * T + t];
-        }
-        off[tid][T] = run;
-    }
-    __syncthreads();
-    for (int32_t t = tid; t < T; t += 256) {
-        m.tab.rng[t] = off[0][t];
-        m.tab.rng[T + t] = off[0][t + 1];
-        m.tab.rng[2 * T + t] = off[1][t];
-        m.tab.rng[3 * T + t] = off[1][t + 1];
-    }
-    for (int32_t t = 0; t < T; ++t) {
-        const int32_t ca = off[0][t + 1] - off[0][t], cr = off[1][t + 1] - off[1][t];
-        for (int32_t j = tid; j < ca; j += 256)
-            m.tab.add_packed[off[0][t] + j] = m.tab.add[(int64_t)t * S + j];
-        for (int32_t j = tid; j < cr; j += 256)
-            m.tab.rem_packed[off[1][t] + j] = m.tab.rem[(int64_t)t * S + j];
-    }
+__global__ void __launch_bounds__(kPT) k_prep(DevModel m) {
+    extern __shared__ __align__(16) char lds[];
+    __shared__ double red[2 * kPT];
+    if (blockIdx.x == 0)
+        prep_scalars(m, red, (double *)lds, (double *)lds + m.S);
+    else
+        prep_tables(m, (uint64_t *)lds);
 }
 
 hipError_t launch_prep(const DevModel &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_prep, dim3(m.T + 1), dim3(256), 0, st, m);
-    hipLaunchKernelGGL(k_pack_tables, dim3(1), dim3(256), 0, st, m);
+    const size_t a = sizeof(double) * ((size_t)m.S + m.T);
+    const size_t b = sizeof(uint64_t) * (size_t)m.T * ((m.S + 63) / 64);
+    hipLaunchKernelGGL(k_prep, dim3(2), dim3(kPT), a > b ? a : b, st, m);
     return hipGetLastError();
 }
 
