@@ -51,6 +51,12 @@ def instance(name):
         # S = MPS_MAX_SCENARIOS = 4096 (128 ore words per block; beyond what
         # the repair walk takes)
         return mpsgen.make_instance(4, 4, 3, 4096, 8, 2.0, 88)
+    if name == "many_jobs":
+        # T x ceil(S/64) = 126 x 16 = 2,016 table jobs: more than one job count
+        # per thread in the scan of the one-launch table rebuild
+        inst = mpsgen.make_instance(3, 3, 2, 1000, 126, 2.0, 90)
+        inst.pcap *= 8.0         # some periods near capacity, not all over it
+        return inst
     if name == "tight":
         inst = mpsgen.make_instance(12, 10, 6, 96, 8, 2.0, 80)
         inst.pcap *= 0.85        # capacities bind in most periods

@@ -25,7 +25,7 @@ def test_objective_parity(name):
 
 
 @pytest.mark.parametrize("name", ["tiny", "ragged", "flat", "single", "tight", "one_period",
-                                  "max_periods", "max_scen"])
+                                  "max_periods", "max_scen", "many_jobs"])
 @pytest.mark.parametrize("never", [False, True])
 def test_eval_exhaustive_small(name, never):
     inst = instance(name)
