@@ -23,12 +23,11 @@
 // 2. the walk: one workgroup of kGW waves.  O[t][s] and M[t] live in LDS
 //    (FP64, summed in placement order, so every capacity decision is the
 //    sequential one bit for bit).  For each block every wave reads the
-//    block's predecessor periods itself (no barrier on the skip path); the
-//    periods from the predecessor bound up are checked eight at a time, one
-//    per wave, each wave testing every scenario with one ballot; the
-//    earliest feasible one is applied to the LDS state and to p.  The next
-//    block's data is loaded while the current one is decided, and its
-//    predecessor periods are patched when the current block is one of them.
+//    block's predecessor periods itself (no barrier and, with the schedule
+//    mirrored in LDS, no global load on the skip path); the periods from the
+//    predecessor bound up are checked eight at a time, one per wave, each
+//    wave testing every scenario with one ballot; the earliest feasible one
+//    is applied to the LDS state and to p.
 #include "internal.h"
 
 namespace mps {
@@ -120,15 +119,23 @@ __global__ void k_greedy_unplace(DevModel m, int8_t *p, const SortItem *a, int32
     order[i] = (int32_t)a[i].idx;
 }
 
-// What a wave holds of one block of the walk.
-struct GBlock {
-    int32_t b;       // block (wave-uniform)
-    double ton;      // tonnage (uniform)
-    int64_t pid;     // lanes 0..MPS_MAX_DEGREE-1: predecessor id or -1
-    int32_t pp;      // its period (T when unplaced; 0 for absent predecessors)
-    uint32_t ore[4]; // ore bits of this lane's scenarios lane + 64 j, j < 4 per group
-};
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, not for its global loads in flight (the coming list ids).
+__device__ __forceinline__ void greedy_lds_sync() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); vmcnt, expcnt untouched
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
+// Most visits of a pass skip their block (a predecessor is still unplaced),
+// so a visit first decides that from what needs no global load on its path:
+// the block id (the list is read 64 ids at a time, the next 64 meanwhile),
+// its predecessor ids (grid arithmetic, or the lists) and their periods
+// (kLP: the schedule mirrored in LDS, one byte per block).  Only a block that
+// may be placed loads its tonnage and ore words.  Without kLP (N too large
+// for LDS) the periods are read from p after full barriers.
+template <bool kLP>
 __global__ void __launch_bounds__(kGT) k_greedy_walk(DevModel m, int8_t *p, int32_t *list0,
                                                      int32_t *list1, int32_t max_pass,
                                                      int32_t *out) {
@@ -136,59 +143,72 @@ __global__ void __launch_bounds__(kGT) k_greedy_walk(DevModel m, int8_t *p, int3
     const int32_t T = m.T, S = m.S;
     double *O = lds;                       // [T][S]
     double *Ml = O + (size_t)T * S;        // [T]
+    int8_t *pl = (int8_t *)(Ml + T);       // [N] when kLP
     __shared__ int32_t best_s[kGW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int64_t i = tid; i < (int64_t)T * S; i += kGT) O[i] = 0.0;
     for (int t = tid; t < T; t += kGT) Ml[t] = 0.0;
+    if (kLP)
+        for (int64_t i = tid; i < m.N; i += kGT) pl[i] = (int8_t)T;   // all unplaced
     __syncthreads();
+    auto sync = [&]() {
+        if (kLP)
+            greedy_lds_sync();
+        else
+            __syncthreads();
+    };
     const int32_t G = (S + 255) / 256;     // groups of 256 scenarios
     int32_t *cur = list0, *nxt = list1;
     int32_t ncur = (int32_t)m.N;
     int32_t passes = 0;
     int64_t placed = 0;
 
-    auto load = [&](int32_t b, int32_t g, GBlock &k) {
-        k.b = b;
-        k.ton = m.ton64[b];
-        k.pid = lane < MPS_MAX_DEGREE ? nbr(m, b, lane, true) : -1;
-        k.pp = k.pid >= 0 ? (int32_t)p[k.pid] : 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int32_t s = g * 256 + lane + 64 * j;
-            k.ore[j] = s < S ? m.ore[(int64_t)(s >> 5) * m.N + b] : 0u;
-        }
-    };
-
     while (passes < max_pass) {
         ++passes;
         int32_t nn = 0;
         int64_t now = 0;
-        GBlock c, n;
-        if (ncur > 0) load(cur[0], 0, c);
+        // list ids [base, base + 64) in ids, the next 64 in flight in ids_next
+        int32_t base = 0;
+        int32_t ids = lane < ncur ? cur[lane] : -1;
+        int32_t ids_next = 64 + lane < ncur ? cur[64 + lane] : -1;
         for (int32_t i = 0; i < ncur; ++i) {
-            if (i + 1 < ncur) load(cur[i + 1], 0, n);
+            if (i == base + 64) {
+                base += 64;
+                ids = ids_next;
+                ids_next = base + 64 + lane < ncur ? cur[base + 64 + lane] : -1;
+            }
+            const int32_t b = __builtin_amdgcn_readlane(ids, i - base);
             // earliest admissible period: every predecessor placed, at or before t
-            int32_t lo = c.pid >= 0 ? c.pp : 0;
+            const int64_t pid = lane < MPS_MAX_DEGREE ? nbr(m, b, lane, true) : -1;
+            int32_t lo = pid >= 0 ? (int32_t)(kLP ? pl[pid] : p[pid]) : 0;
             for (int o = 1; o < kMaxPred; o <<= 1) lo = max(lo, __shfl_xor(lo, o));
             lo = __builtin_amdgcn_readfirstlane(lo);
             int32_t tb = T;
+            double ton = 0.0;
             if (lo < T) {
+                ton = m.ton64[b];
+                uint32_t ore0[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int32_t s = lane + 64 * j;
+                    ore0[j] = s < S ? m.ore[(int64_t)(s >> 5) * m.N + b] : 0u;
+                }
                 for (int32_t t0 = lo; t0 < T && tb == T; t0 += kGW) {
                     const int32_t t = t0 + wave;
                     bool bad = true;
                     if (t < T) {
-                        bad = !(Ml[t] + c.ton <= m.mcap);
+                        bad = !(Ml[t] + ton <= m.mcap);
                         const double *Ot = O + (size_t)t * S;
                         for (int32_t g = 0; g < G && !bad; ++g) {
                             uint32_t orw[4];
                             if (g == 0) {
 #pragma unroll
-                                for (int j = 0; j < 4; ++j) orw[j] = c.ore[j];
+                                for (int j = 0; j < 4; ++j) orw[j] = ore0[j];
                             } else {
 #pragma unroll
                                 for (int j = 0; j < 4; ++j) {
                                     const int32_t s = g * 256 + lane + 64 * j;
-                                    orw[j] = s < S ? m.ore[(int64_t)(s >> 5) * m.N + c.b] : 0u;
+                                    orw[j] = s < S ? m.ore[(int64_t)(s >> 5) * m.N + b] : 0u;
                                 }
                             }
                             bool v = false;
@@ -196,38 +216,35 @@ __global__ void __launch_bounds__(kGT) k_greedy_walk(DevModel m, int8_t *p, int3
                             for (int j = 0; j < 4; ++j) {
                                 const int32_t s = g * 256 + lane + 64 * j;
                                 if (s < S && ((orw[j] >> (s & 31)) & 1u))
-                                    v = v || !(Ot[s] + c.ton <= m.pcap);
+                                    v = v || !(Ot[s] + ton <= m.pcap);
                             }
                             bad = __ballot(v) != 0ull;
                         }
                     }
                     if (lane == 0) best_s[wave] = bad ? T : t;
-                    __syncthreads();
+                    sync();
                     int32_t bt = T;
 #pragma unroll
                     for (int w = 0; w < kGW; ++w) bt = min(bt, best_s[w]);
                     tb = bt;
-                    __syncthreads();   // best_s is rewritten by the next round
+                    sync();   // best_s is rewritten by the next round
                 }
             }
             if (tb < T) {
-                const double ton = c.ton;
                 double *Ot = O + (size_t)tb * S;
                 for (int32_t s = tid; s < S; s += kGT)
-                    if ((m.ore[(int64_t)(s >> 5) * m.N + c.b] >> (s & 31)) & 1u) Ot[s] += ton;
+                    if ((m.ore[(int64_t)(s >> 5) * m.N + b] >> (s & 31)) & 1u) Ot[s] += ton;
                 if (tid == 0) {
                     Ml[tb] += ton;
-                    p[c.b] = (int8_t)tb;
+                    p[b] = (int8_t)tb;
+                    if (kLP) pl[b] = (int8_t)tb;
                 }
                 ++now;
-                __syncthreads();
-                // the next block may have this one as a predecessor
-                if (n.pid == c.b) n.pp = tb;
+                sync();
             } else {
-                if (tid == 0) nxt[nn] = c.b;
+                if (tid == 0) nxt[nn] = b;
                 ++nn;
             }
-            c = n;
         }
         // the next pass reads the list wave 0 has just written
         __syncthreads();
@@ -254,6 +271,10 @@ size_t greedy_lds_bytes(const DevModel &m) {
     return 8 * ((size_t)m.T * m.S + m.T) + 64;   // + the round results (static)
 }
 
+static size_t greedy_lds_map_bytes(const DevModel &m) {
+    return greedy_lds_bytes(m) + (size_t)m.N;
+}
+
 hipError_t launch_greedy(const DevModel &m, int8_t *p, int32_t max_pass, void *ws,
                          int32_t *out, hipStream_t st) {
     int64_t n2 = kSortLocal;
@@ -275,8 +296,17 @@ hipError_t launch_greedy(const DevModel &m, int8_t *p, int32_t max_pass, void *w
     }
     hipLaunchKernelGGL(k_greedy_unplace, dim3((unsigned)((m.N + 255) / 256)), dim3(256), 0, st,
                        m, p, a, l0);
-    hipLaunchKernelGGL(k_greedy_walk, dim3(1), dim3(kGT), greedy_lds_bytes(m), st, m, p, l0, l1,
-                       max_pass, out);
+    int dev = 0, max_lds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    if (greedy_lds_map_bytes(m) <= (size_t)max_lds)
+        hipLaunchKernelGGL(k_greedy_walk<true>, dim3(1), dim3(kGT), greedy_lds_map_bytes(m), st,
+                           m, p, l0, l1, max_pass, out);
+    else
+        hipLaunchKernelGGL(k_greedy_walk<false>, dim3(1), dim3(kGT), greedy_lds_bytes(m), st, m,
+                           p, l0, l1, max_pass, out);
     return hipGetLastError();
 }
 
